@@ -1,0 +1,149 @@
+/*
+ * qb.h -- C ABI of the MI355X (gfx950) solver for the spatially inhomogeneous
+ * matrix-valued quantum Boltzmann equation of Lu & Mendl, arXiv:1408.1782:
+ *
+ *     d_t W + v_x d_x W = C[W] - i [B . sigma, W]                 (eq. boltzmann)
+ *
+ * W(x, v) is a 2x2 Hermitian matrix on x in (0, 1) (Nx finite-volume cells,
+ * centres (j + 1/2)/Nx) and v on the N x N grid v_i = (2L/N)(i - N/2),
+ * i = 0..N-1 (Sec. 5.1); the first velocity axis is v_x.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is a DEVICE pointer (e.g. from torch) unless
+ *   noted; calls are asynchronous on `stream` (a hipStream_t; NULL = default
+ *   stream).  The library never frees caller memory.
+ * State layout.  W and C are [cells][N][N][2][2] complex, row-major, complex
+ *   interleaved (re, im): complex128 for QB_F64 plans, complex64 for QB_F32.
+ *   Only the Hermitian part of W is read (components w_mu =
+ *   (1/2) Re tr(sigma_mu W), Sec. 3.1, eq. spin_repr).
+ * Field.  B is float64 [Nx][3] (B_1, B_2, B_3) on every plan.
+ * Moments.  float64 [Nx][7] per snapshot: rho_0..rho_3 = h^2 sum_v w_mu
+ *   (eq. density in Pauli components), p_x, p_y = h^2 sum_v v tr W
+ *   (eq. velocity times tr rho), e = h^2 sum_v |v|^2/2 tr W
+ *   (eq. internal_energy plus the kinetic part), h = 2L/N.
+ * Errors.  Every call validates its arguments before enqueuing anything;
+ *   on error it returns a negative qb_status and enqueues nothing.
+ *   QB_EHIP reports a failed HIP call (launch or allocation); the text of
+ *   the last error is available from qb_last_error().
+ * Threads.  A plan may be used by one stream at a time; distinct plans are
+ *   independent.
+ */
+#ifndef QB_H
+#define QB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QB_OK = 0,
+  QB_EINVAL = -1,     /* bad argument (null pointer, size, range)          */
+  QB_ENOTSUP = -2,    /* valid but unsupported (N not 16/32/64, odd J)      */
+  QB_ECFL = -3,       /* (dt/2) max|v_x| / dx > 1 for the transport step    */
+  QB_EWORKSPACE = -4, /* more cells than the plan was created for           */
+  QB_EHIP = -5        /* HIP runtime error                                  */
+} qb_status;
+
+typedef enum { QB_F64 = 0, QB_F32 = 1 } qb_precision;
+
+typedef enum { QB_PERIODIC = 0, QB_DIRICHLET = 1, QB_MAXWELL = 2 } qb_bc_kind;
+
+/* Fermi-Dirac state W_FD(v) = U diag(f_up, f_down) U^H,
+ * f_s = 1 / (exp((|v|^2/2 - mu_s) inv_kT) + 1)        (eq. W_FermiDirac).
+ * U is row-major, its columns are the spin basis (Table 1). */
+typedef struct {
+  double inv_kT, mu_up, mu_down;
+  double U_re[4], U_im[4];
+} qb_fd;
+
+/* Boundary condition on one wall (Sec. 2).
+ *   QB_PERIODIC : both walls must be periodic.
+ *   QB_DIRICHLET: incoming velocities see Phi = W_FD(state).
+ *   QB_MAXWELL  : incoming velocities see (1 - alpha) W_b(-v_x, v_y)
+ *                 + alpha W_FD(state) Fbar / Z, W_b the adjacent cell,
+ *                 Fbar its outgoing number flux, Z the incoming flux of
+ *                 W_FD; 0 <= alpha <= 1.
+ * Ghost cells (two per wall): the inflow state at incoming v_x, a copy of
+ * the adjacent cell otherwise; the row v_x = -L has no mirror and counts as
+ * outgoing at the right wall. */
+typedef struct {
+  int32_t kind; /* qb_bc_kind */
+  qb_fd state;
+  double alpha;
+} qb_bc;
+
+/* Problem description.
+ *   Nx    : number of cells (>= 1).
+ *   N     : velocity grid side, 16, 32 or 64.
+ *   J     : number of angles theta_j (eq. theta_grid), even, 2..128.
+ *   M     : Gauss-Legendre radii of eq. approxH-JM, 1..256.
+ *   L, R  : velocity half-box (periodization on [-L, L]^2) and truncation
+ *           radius of the collision integrals (Sec. 3.2); L > 0, R >= 0.
+ *   precision : QB_F64 (complex128 state, float64 arithmetic) or QB_F32
+ *           (complex64 state, float32 collision and transport arithmetic,
+ *           float64 moments).
+ */
+typedef struct {
+  int32_t Nx, N, J, M;
+  double L, R;
+  int32_t precision; /* qb_precision */
+  qb_bc left, right;
+} qb_problem;
+
+typedef struct qb_plan_s* qb_plan;
+
+/* Create a plan: validates the problem, builds the quadrature tables of
+ * Sec. 3.2 (theta grids, phi_R, psi_R, omega_G, omega_H, Gauss-Legendre
+ * nodes, modulation phases) on the host in float64, and allocates every
+ * device buffer the other calls need for up to Nx cells on the current
+ * HIP device.  Synchronous.  *out receives the plan (NULL on error). */
+qb_status qb_plan_create(const qb_problem* problem, qb_plan* out);
+
+/* Free a plan and its device memory (synchronizes the device first). */
+qb_status qb_plan_destroy(qb_plan plan);
+
+/* Device bytes held by a plan. */
+size_t qb_plan_bytes(qb_plan plan);
+
+/* C = C[W] = C_c[W] + C_d[W] for `ncells` independent cells (Sec. 3.2):
+ * the conservative part through the principal-value kernel G (eq. approxG)
+ * and the dissipative part through H (eq. approxH-J, eq. approxH-JM), in
+ * the Carleman form of eq. CcPauli / eq. CdPauli; Fourier coefficients on
+ * Xi (eq. fourier_grid) with the -N/2 rows and columns set to zero on input
+ * and output, products on the 2N zero-padded grid.
+ * W, C: [ncells][N][N][2][2] complex, distinct buffers; 1 <= ncells <= Nx. */
+qb_status qb_collision(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream);
+
+/* One finite-volume transport step of length dt in place (eq.
+ * slopeLimiterStep with the minmod limiter of eq. minmod, applied to the
+ * four Pauli components), with the plan's boundary conditions.
+ * W: [Nx][N][N][2][2] complex.  QB_ECFL if dt max|v_x| Nx > 1. */
+qb_status qb_transport_step(qb_plan plan, void* W, double dt, void* stream);
+
+/* nsteps time steps of the splitting scheme of Sec. 4 in place: transport
+ * over dt/2, one Heun (two-stage Runge-Kutta) step of length dt for
+ * dW/dt = C[W] - i[B . sigma, W] per cell, transport over dt/2.
+ * W: [Nx][N][N][2][2] complex; B: float64 [Nx][3] device array or NULL
+ * (no field); moments: float64 [nsteps + 1][Nx][7] device array or NULL
+ * (snapshot 0 is the initial state). */
+qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, double* moments,
+                  void* stream);
+
+/* float64 moments [Nx][7] of W ([Nx][N][N][2][2] complex). */
+qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
+
+/* Human-readable name of a status; text of the last HIP error seen. */
+const char* qb_strerror(qb_status status);
+const char* qb_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t qb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QB_H */

@@ -1,0 +1,287 @@
+"""ctypes binding of libqb.so (include/qb.h): argument marshalling only.
+
+Every numerical step runs in the HIP library.  Tensors passed in must be
+contiguous CUDA (HIP) tensors of the dtype the plan expects; the binding
+checks shapes and dtypes, passes raw device pointers and the current torch
+stream, and raises QBError on any non-zero status.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_NAME = "libqb.so"
+
+QB_OK, QB_EINVAL, QB_ENOTSUP, QB_ECFL, QB_EWORKSPACE, QB_EHIP = 0, -1, -2, -3, -4, -5
+QB_F64, QB_F32 = 0, 1
+QB_PERIODIC, QB_DIRICHLET, QB_MAXWELL = 0, 1, 2
+_KINDS = {"periodic": QB_PERIODIC, "dirichlet": QB_DIRICHLET, "maxwell": QB_MAXWELL}
+
+# names the header declares (checked by the CPU tests)
+EXPORTS = (
+    "qb_plan_create",
+    "qb_plan_destroy",
+    "qb_plan_bytes",
+    "qb_collision",
+    "qb_transport_step",
+    "qb_step",
+    "qb_moments",
+    "qb_strerror",
+    "qb_last_error",
+    "qb_version",
+)
+
+
+class QBError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        msg = _strerror(status)
+        if status == QB_EHIP and _LIB is not None:
+            msg += ": " + _LIB.qb_last_error().decode()
+        super().__init__(f"{what}: {msg} (status {status})")
+
+
+class _FD(ctypes.Structure):
+    _fields_ = [
+        ("inv_kT", ctypes.c_double),
+        ("mu_up", ctypes.c_double),
+        ("mu_down", ctypes.c_double),
+        ("U_re", ctypes.c_double * 4),
+        ("U_im", ctypes.c_double * 4),
+    ]
+
+
+class _BC(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("state", _FD), ("alpha", ctypes.c_double)]
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("Nx", ctypes.c_int32),
+        ("N", ctypes.c_int32),
+        ("J", ctypes.c_int32),
+        ("M", ctypes.c_int32),
+        ("L", ctypes.c_double),
+        ("R", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("left", _BC),
+        ("right", _BC),
+    ]
+
+
+_LIB = None
+
+
+def lib_path():
+    return os.path.join(HERE, LIB_NAME)
+
+
+def _declare(lib):
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.qb_plan_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(vp)]
+    lib.qb_plan_create.restype = i32
+    lib.qb_plan_destroy.argtypes = [vp]
+    lib.qb_plan_destroy.restype = i32
+    lib.qb_plan_bytes.argtypes = [vp]
+    lib.qb_plan_bytes.restype = ctypes.c_size_t
+    lib.qb_collision.argtypes = [vp, vp, vp, i32, vp]
+    lib.qb_collision.restype = i32
+    lib.qb_transport_step.argtypes = [vp, vp, dbl, vp]
+    lib.qb_transport_step.restype = i32
+    lib.qb_step.argtypes = [vp, vp, vp, dbl, i32, vp, vp]
+    lib.qb_step.restype = i32
+    lib.qb_moments.argtypes = [vp, vp, vp, vp]
+    lib.qb_moments.restype = i32
+    lib.qb_strerror.argtypes = [i32]
+    lib.qb_strerror.restype = ctypes.c_char_p
+    lib.qb_last_error.argtypes = []
+    lib.qb_last_error.restype = ctypes.c_char_p
+    lib.qb_version.argtypes = []
+    lib.qb_version.restype = i32
+
+
+def load():
+    """Load libqb.so (built in-tree by build.py); raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise FileNotFoundError(
+                f"{path} is not built; run `python -m paper_1408_1782_amd.build` "
+                "(or __graft_entry__.build())"
+            )
+        lib = ctypes.CDLL(path)
+        _declare(lib)
+        _LIB = lib
+    return _LIB
+
+
+def _strerror(status):
+    if _LIB is None:
+        return f"status {status}"
+    return _LIB.qb_strerror(status).decode()
+
+
+def _check(status, what):
+    if status != QB_OK:
+        raise QBError(status, what)
+
+
+class BC:
+    """Boundary condition on one wall: kind in {'periodic', 'dirichlet',
+    'maxwell'}, Fermi-Dirac wall state (inv_kT, mu_up, mu_down, U) and the
+    Maxwell accommodation coefficient alpha."""
+
+    def __init__(self, kind="periodic", inv_kT=1.0, mu_up=0.0, mu_down=0.0, U=None, alpha=0.0):
+        self.kind, self.inv_kT, self.mu_up, self.mu_down = kind, inv_kT, mu_up, mu_down
+        self.U = U
+        self.alpha = alpha
+
+    @classmethod
+    def from_workload(cls, b):
+        return cls(b.kind, b.inv_kT, b.mu_up, b.mu_down, b.U, b.alpha)
+
+    def _c(self):
+        c = _BC()
+        c.kind = _KINDS[self.kind]
+        c.alpha = float(self.alpha)
+        c.state.inv_kT = float(self.inv_kT)
+        c.state.mu_up = float(self.mu_up)
+        c.state.mu_down = float(self.mu_down)
+        U = [[1, 0], [0, 1]] if self.U is None else self.U
+        for a in range(2):
+            for b in range(2):
+                z = complex(U[a][b])
+                c.state.U_re[2 * a + b] = z.real
+                c.state.U_im[2 * a + b] = z.imag
+        return c
+
+
+class Problem:
+    def __init__(self, Nx, N, J=32, M=None, L=12.0, R=7.5, precision="f64", left=None, right=None):
+        self.Nx, self.N, self.J = int(Nx), int(N), int(J)
+        self.M = int(N if M is None else M)
+        self.L, self.R = float(L), float(R)
+        self.precision = precision
+        self.left = left or BC("periodic")
+        self.right = right or BC("periodic")
+
+    def _c(self):
+        p = _Problem()
+        p.Nx, p.N, p.J, p.M = self.Nx, self.N, self.J, self.M
+        p.L, p.R = self.L, self.R
+        p.precision = QB_F64 if self.precision == "f64" else QB_F32
+        p.left, p.right = self.left._c(), self.right._c()
+        return p
+
+
+def _stream():
+    import torch
+
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A qb_plan: quadrature tables and device buffers for one problem."""
+
+    def __init__(self, problem):
+        import torch
+
+        self.lib = load()
+        self.problem = problem
+        self.cdtype = torch.complex128 if problem.precision == "f64" else torch.complex64
+        h = ctypes.c_void_p()
+        pc = problem._c()
+        _check(self.lib.qb_plan_create(ctypes.byref(pc), ctypes.byref(h)), "qb_plan_create")
+        self.handle = h
+
+    @property
+    def nbytes(self):
+        return self.lib.qb_plan_bytes(self.handle)
+
+    def _check_state(self, W, ncells=None):
+        p = self.problem
+        n = p.Nx if ncells is None else ncells
+        if not W.is_cuda or not W.is_contiguous() or W.dtype != self.cdtype:
+            raise ValueError(f"expected a contiguous CUDA {self.cdtype} tensor")
+        if tuple(W.shape[1:]) != (p.N, p.N, 2, 2) or W.shape[0] < n:
+            raise ValueError(f"expected shape [{n}, {p.N}, {p.N}, 2, 2], got {tuple(W.shape)}")
+
+    def collision(self, W, C=None, ncells=None):
+        """qb_collision: C[W] for the first `ncells` cells of W."""
+        import torch
+
+        n = W.shape[0] if ncells is None else int(ncells)
+        self._check_state(W, n)
+        if C is None:
+            C = torch.empty_like(W)
+        self._check_state(C, n)
+        _check(self.lib.qb_collision(self.handle, _ptr(W), _ptr(C), n, _stream()), "qb_collision")
+        return C
+
+    def transport_step(self, W, dt):
+        """qb_transport_step: one limited transport step of length dt, in place."""
+        self._check_state(W)
+        _check(self.lib.qb_transport_step(self.handle, _ptr(W), float(dt), _stream()), "qb_transport_step")
+        return W
+
+    def step(self, W, B=None, dt=1e-3, nsteps=1, moments=None):
+        """qb_step: nsteps splitting steps in place; B float64 [Nx, 3] or None;
+        moments float64 [nsteps + 1, Nx, 7] or None."""
+        import torch
+
+        self._check_state(W)
+        p = self.problem
+        bp = ctypes.c_void_p(0)
+        if B is not None:
+            if B.dtype != torch.float64 or not B.is_cuda or tuple(B.shape) != (p.Nx, 3) or not B.is_contiguous():
+                raise ValueError("B must be a contiguous CUDA float64 tensor [Nx, 3]")
+            bp = _ptr(B)
+        mp = ctypes.c_void_p(0)
+        if moments is not None:
+            if moments.dtype != torch.float64 or tuple(moments.shape) != (nsteps + 1, p.Nx, 7):
+                raise ValueError("moments must be CUDA float64 [nsteps + 1, Nx, 7]")
+            mp = _ptr(moments)
+        _check(self.lib.qb_step(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _stream()), "qb_step")
+        return W
+
+    def moments(self, W, out=None):
+        """qb_moments: float64 [Nx, 7] moments of W."""
+        import torch
+
+        self._check_state(W)
+        if out is None:
+            out = torch.empty((self.problem.Nx, 7), dtype=torch.float64, device=W.device)
+        _check(self.lib.qb_moments(self.handle, _ptr(W), _ptr(out), _stream()), "qb_moments")
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.qb_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# C-ABI names, for callers that prefer them
+def qb_collision(plan, W, C=None, ncells=None):
+    return plan.collision(W, C, ncells)
+
+
+def qb_transport_step(plan, W, dt):
+    return plan.transport_step(W, dt)
+
+
+def qb_step(plan, W, B=None, dt=1e-3, nsteps=1, moments=None):
+    return plan.step(W, B, dt, nsteps, moments)
+
+
+def qb_moments(plan, W, out=None):
+    return plan.moments(W, out)

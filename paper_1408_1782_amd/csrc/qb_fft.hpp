@@ -1,0 +1,366 @@
+// Register-resident 2D FFT engine for gfx950 (wave64).
+//
+// A P x P complex field is spread over NT = P * TPR threads of a workgroup,
+// TPR = P / E threads per line, E elements per thread.  Thread t owns line
+// l = t / TPR and lane-in-line q = t % TPR (the TPR lanes of a line are
+// adjacent lanes of one wavefront).
+//
+//   "strided"  layout: element index  x = q + TPR * n,        n = 0..E-1
+//   "blocked"  layout: element index  k + E * bitrev(q),      k = 0..E-1
+//
+// A forward line transform takes strided data to blocked spectra: an E-point
+// FFT in registers on the stride-TPR subsequence, a twiddle w_P^{q k}, then a
+// TPR-point DFT across the lanes (radix-2 decimation in frequency through
+// lane shuffles, which leaves the output blocks in bit-reversed lane order).
+// The inverse line transform runs the same steps backwards.  Both are
+// unnormalized: inv(fwd(x)) = P x.
+//
+// 2D: rows (index x, line = y) and columns (index y, line = kx).  The field
+// moves between row and column ownership through an LDS transpose, one real
+// component at a time, so the LDS buffer holds P * (P + 1) scalars.
+//
+//   row real (strided in x) --fwd rows--> row spectra (blocked in kx)
+//     --T1--> column real (strided in y) --fwd cols--> column spectra
+//   and back with the inverse transforms and T2.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <utility>
+
+namespace qb {
+
+// ------------------------------------------------------------------ constexpr trig
+// Taylor series after reduction to [-pi/4, pi/4]; used only for the compile-time
+// twiddles of the in-register transforms.
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+constexpr double cx_sin_small(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double cx_cos_small(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// cos / sin of 2 pi a / b for integers 0 <= a < b, b a power of two.
+constexpr double cx_cos_frac(int a, int b) {
+  // octant reduction: angle = 2 pi a / b = (pi/4) * (8a/b)
+  const int a8 = a * 8;
+  const int oct = a8 / b;               // 0..7
+  const double r = (double)(a8 - oct * b) / b * (kPi / 4.0);  // [0, pi/4)
+  switch (oct) {
+    case 0: return cx_cos_small(r);
+    case 1: return cx_sin_small(kPi / 4.0 - r);
+    case 2: return -cx_sin_small(r);
+    case 3: return -cx_cos_small(kPi / 4.0 - r);
+    case 4: return -cx_cos_small(r);
+    case 5: return -cx_sin_small(kPi / 4.0 - r);
+    case 6: return cx_sin_small(r);
+    default: return cx_cos_small(kPi / 4.0 - r);
+  }
+}
+constexpr double cx_sin_frac(int a, int b) {
+  const int a8 = a * 8;
+  const int oct = a8 / b;
+  const double r = (double)(a8 - oct * b) / b * (kPi / 4.0);
+  switch (oct) {
+    case 0: return cx_sin_small(r);
+    case 1: return cx_cos_small(kPi / 4.0 - r);
+    case 2: return cx_cos_small(r);
+    case 3: return cx_sin_small(kPi / 4.0 - r);
+    case 4: return -cx_sin_small(r);
+    case 5: return -cx_cos_small(kPi / 4.0 - r);
+    case 6: return -cx_cos_small(r);
+    default: return -cx_sin_small(kPi / 4.0 - r);
+  }
+}
+
+template <int A, int B>
+struct Tw {
+  static constexpr double c = cx_cos_frac(A, B);
+  static constexpr double s = cx_sin_frac(A, B);
+};
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int bitrev_c(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+__host__ __device__ inline int bitrev_rt(int v, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((v >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// ------------------------------------------------------------------ in-register FFT
+// y[k] = sum_n x[O + S n] exp(DIR * 2 pi i n k / E), natural order in and out.
+template <typename T, int E, int DIR>
+struct RegFft {
+  template <int S, int O, int IN_N>
+  static __device__ __forceinline__ void run(const T (&xr)[IN_N], const T (&xi)[IN_N], T (&yr)[E],
+                                             T (&yi)[E]) {
+    if constexpr (E == 1) {
+      yr[0] = xr[O];
+      yi[0] = xi[O];
+    } else {
+      constexpr int H = E / 2;
+      T er[H], ei[H], orr[H], oi[H];
+      RegFft<T, H, DIR>::template run<2 * S, O, IN_N>(xr, xi, er, ei);
+      RegFft<T, H, DIR>::template run<2 * S, O + S, IN_N>(xr, xi, orr, oi);
+      butterflies(er, ei, orr, oi, yr, yi, std::make_integer_sequence<int, H>{});
+    }
+  }
+
+  template <int H, int... K>
+  static __device__ __forceinline__ void butterflies(const T (&er)[H], const T (&ei)[H], const T (&orr)[H],
+                                                     const T (&oi)[H], T (&yr)[E], T (&yi)[E],
+                                                     std::integer_sequence<int, K...>) {
+    (bfly<H, K>(er, ei, orr, oi, yr, yi), ...);
+  }
+
+  template <int H, int K>
+  static __device__ __forceinline__ void bfly(const T (&er)[H], const T (&ei)[H], const T (&orr)[H],
+                                              const T (&oi)[H], T (&yr)[E], T (&yi)[E]) {
+    T tr, ti;
+    if constexpr (K == 0) {
+      tr = orr[K];
+      ti = oi[K];
+    } else if constexpr (4 * K == E) {
+      // w = exp(DIR * i pi / 2) = DIR * i
+      if constexpr (DIR < 0) {
+        tr = oi[K];
+        ti = -orr[K];
+      } else {
+        tr = -oi[K];
+        ti = orr[K];
+      }
+    } else {
+      constexpr T c = (T)Tw<K, E>::c;
+      constexpr T s = (T)(DIR * Tw<K, E>::s);
+      tr = orr[K] * c - oi[K] * s;
+      ti = orr[K] * s + oi[K] * c;
+    }
+    yr[K] = er[K] + tr;
+    yi[K] = ei[K] + ti;
+    yr[K + H] = er[K] - tr;
+    yi[K + H] = ei[K] - ti;
+  }
+};
+
+template <typename T, int E, int DIR>
+__device__ __forceinline__ void reg_fft(T (&zr)[E], T (&zi)[E]) {
+  T yr[E], yi[E];
+  RegFft<T, E, DIR>::template run<1, 0, E>(zr, zi, yr, yi);
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    zr[k] = yr[k];
+    zi[k] = yi[k];
+  }
+}
+
+// ------------------------------------------------------------------ lane shuffles
+// Value of lane (lane ^ MASK) for MASK in {1, 2, 4}, by DPP moves within a row
+// of 16 lanes: quad_perm for 1 and 2, quad_perm [3,2,1,0] then
+// row_half_mirror (lane i -> 7 - i in each group of 8) for 4.
+template <int MASK>
+__device__ __forceinline__ int xor_lane_i32(int v) {
+  if constexpr (MASK == 1) {
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (MASK == 2) {
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else {
+    static_assert(MASK == 4, "lane mask must be 1, 2 or 4");
+    const int t = __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
+    return __builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false);        // row_half_mirror
+  }
+}
+
+template <int MASK>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __int_as_float(xor_lane_i32<MASK>(__float_as_int(v)));
+}
+
+template <int MASK>
+__device__ __forceinline__ double xor_lane(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = xor_lane_i32<MASK>((int)(b & 0xffffffffll));
+  const int hi = xor_lane_i32<MASK>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// cos / sin of 2 pi j / m for m in {2, 4, 8}, 0 <= j < m / 2 (lane-stage twiddles)
+__device__ __forceinline__ void small_twiddle(int j, int m, double& c, double& s) {
+  const double r2 = 0.70710678118654752440084436210484904;
+  const int a = j * (8 / m);  // eighths of a turn, 0..3
+  c = a == 0 ? 1.0 : (a == 1 ? r2 : (a == 2 ? 0.0 : -r2));
+  s = a == 0 ? 0.0 : (a == 2 ? 1.0 : r2);
+}
+
+// ------------------------------------------------------------------ engine
+template <typename T, int P_, int E_>
+struct Fft2 {
+  static constexpr int P = P_;
+  static constexpr int E = E_;
+  static constexpr int TPR = P / E;
+  static constexpr int NT = P * TPR;
+  static constexpr int LB = ilog2(TPR);
+  static constexpr int LD = P + 1;          // padded LDS row
+  static constexpr int LDS_SCALARS = P * LD;
+  static_assert(TPR >= 1 && TPR <= 8 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2, 4 or 8");
+  static_assert(E * TPR == P, "E * TPR must equal P");
+
+  int t, line, q, bq;
+  T* lds;          // transpose buffer, LDS_SCALARS scalars
+  const T* twc;    // LDS: cos(2 pi i / P), i < P
+  const T* tws;    // LDS: sin(2 pi i / P)
+
+  __device__ __forceinline__ void init(T* lds_buf, const T* tc, const T* ts) {
+    t = threadIdx.x;
+    line = t / TPR;
+    q = t % TPR;
+    bq = bitrev_rt(q, LB);
+    lds = lds_buf;
+    twc = tc;
+    tws = ts;
+  }
+  __device__ __forceinline__ int sx(int n) const { return q + TPR * n; }     // strided index
+  __device__ __forceinline__ int bk(int k) const { return k + E * bq; }      // blocked index
+
+  // forward: strided -> blocked, exp(-2 pi i ...)
+  __device__ __forceinline__ void fwd_line(T (&zr)[E], T (&zi)[E]) const {
+    reg_fft<T, E, -1>(zr, zi);
+    if constexpr (TPR > 1) {
+#pragma unroll
+      for (int k = 1; k < E; ++k) {
+        const int idx = (q * k) & (P - 1);
+        const T c = twc[idx], s = -tws[idx];
+        const T r = zr[k] * c - zi[k] * s;
+        zi[k] = zr[k] * s + zi[k] * c;
+        zr[k] = r;
+      }
+      lane_fwd<TPR / 2>(zr, zi);
+    }
+  }
+
+  // one radix-2 decimation-in-frequency stage across lanes q and q ^ H
+  template <int H>
+  __device__ __forceinline__ void lane_fwd(T (&zr)[E], T (&zi)[E]) const {
+    if constexpr (H >= 1) {
+      const bool upper = (q & H) != 0;
+      double cd, sd;
+      small_twiddle(q & (H - 1), 2 * H, cd, sd);
+      const T c = (T)cd, s = (T)(-sd);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T orr = xor_lane<H>(zr[k]);
+        const T oi = xor_lane<H>(zi[k]);
+        if (!upper) {
+          zr[k] = zr[k] + orr;
+          zi[k] = zi[k] + oi;
+        } else {
+          const T dr = orr - zr[k], di = oi - zi[k];
+          zr[k] = dr * c - di * s;
+          zi[k] = dr * s + di * c;
+        }
+      }
+      lane_fwd<H / 2>(zr, zi);
+    }
+  }
+
+  // inverse of lane_fwd<H> (times 2), stages in increasing H
+  template <int H>
+  __device__ __forceinline__ void lane_inv(T (&zr)[E], T (&zi)[E]) const {
+    if constexpr (H <= TPR / 2) {
+      const bool upper = (q & H) != 0;
+      double cd, sd;
+      small_twiddle(q & (H - 1), 2 * H, cd, sd);
+      const T c = (T)cd, s = (T)sd;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        if (upper) {
+          const T r = zr[k] * c - zi[k] * s;
+          zi[k] = zr[k] * s + zi[k] * c;
+          zr[k] = r;
+        }
+        const T orr = xor_lane<H>(zr[k]);
+        const T oi = xor_lane<H>(zi[k]);
+        if (!upper) {
+          zr[k] = zr[k] + orr;
+          zi[k] = zi[k] + oi;
+        } else {
+          zr[k] = orr - zr[k];
+          zi[k] = oi - zi[k];
+        }
+      }
+      lane_inv<H * 2>(zr, zi);
+    }
+  }
+
+  // inverse: blocked -> strided, exp(+2 pi i ...), unnormalized
+  __device__ __forceinline__ void inv_line(T (&zr)[E], T (&zi)[E]) const {
+    if constexpr (TPR > 1) {
+      lane_inv<1>(zr, zi);
+#pragma unroll
+      for (int k = 1; k < E; ++k) {
+        const int idx = (q * k) & (P - 1);
+        const T c = twc[idx], s = tws[idx];
+        const T r = zr[k] * c - zi[k] * s;
+        zi[k] = zr[k] * s + zi[k] * c;
+        zr[k] = r;
+      }
+    }
+    reg_fft<T, E, +1>(zr, zi);
+  }
+
+  // T1: row spectra (blocked in kx, line = y) -> column real (strided in y, line = kx)
+  __device__ __forceinline__ void t_rows_to_cols(T (&zr)[E], T (&zi)[E]) const {
+    xpose_rb_to_cs(zr);
+    xpose_rb_to_cs(zi);
+  }
+  // T2: column real (strided in y, line = kx) -> row spectra (blocked in kx, line = y)
+  __device__ __forceinline__ void t_cols_to_rows(T (&zr)[E], T (&zi)[E]) const {
+    xpose_cs_to_rb(zr);
+    xpose_cs_to_rb(zi);
+  }
+
+  __device__ __forceinline__ void xpose_rb_to_cs(T (&z)[E]) const {
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[bk(k) * LD + line] = z[k];
+    __syncthreads();
+#pragma unroll
+    for (int n = 0; n < E; ++n) z[n] = lds[line * LD + sx(n)];
+    __syncthreads();
+  }
+  __device__ __forceinline__ void xpose_cs_to_rb(T (&z)[E]) const {
+#pragma unroll
+    for (int n = 0; n < E; ++n) lds[line * LD + sx(n)] = z[n];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) z[k] = lds[bk(k) * LD + line];
+    __syncthreads();
+  }
+
+  // full 2D: row real -> column spectra
+  __device__ __forceinline__ void fwd2(T (&zr)[E], T (&zi)[E]) const {
+    fwd_line(zr, zi);
+    t_rows_to_cols(zr, zi);
+    fwd_line(zr, zi);
+  }
+  // full 2D: column spectra -> row real
+  __device__ __forceinline__ void inv2(T (&zr)[E], T (&zi)[E]) const {
+    inv_line(zr, zi);
+    t_cols_to_rows(zr, zi);
+    inv_line(zr, zi);
+  }
+};
+
+}  // namespace qb

@@ -1,0 +1,635 @@
+// Device kernels of the spectral collision operator, transport and time step.
+//
+// Internal layouts (all per cell):
+//   state     w[mu][cell][i][j], mu = 0..3 Pauli components (Sec. 3.1), on the
+//             velocity grid v = (2L/N)(i - N/2, j - N/2).
+//   P grid    the 2N x 2N zero-padded grid (Sec. 3.2), stored in FFT order:
+//             real-space index x = p mod P for p in [-N, N-1] (spacing L/N, the
+//             velocity grid sits on the even points), frequency index k = b mod P.
+//   row real  real-space field, "strided" engine layout: element (x, y) lives
+//             in thread t = y*TPR + x%TPR, slot n = x/TPR, stored at n*NT + t.
+//   col spec  spectrum, "blocked" layout: element (kx, ky) lives in thread
+//             t = kx*TPR + bitrev(ky/E), slot k = ky%E, stored at k*NT + t
+//             (real and imaginary planes separately).
+#pragma once
+#include "qb_fft.hpp"
+
+namespace qb {
+
+template <typename T, int P>
+struct Cfg;
+template <>
+struct Cfg<double, 32> { static constexpr int E = 16; };
+template <>
+struct Cfg<double, 64> { static constexpr int E = 16; };
+template <>
+struct Cfg<double, 128> { static constexpr int E = 16; };
+template <>
+struct Cfg<float, 32> { static constexpr int E = 16; };
+template <>
+struct Cfg<float, 64> { static constexpr int E = 16; };
+template <>
+struct Cfg<float, 128> { static constexpr int E = 16; };
+
+// Device-side view of the plan's tables and buffers (all device pointers).
+template <typename T>
+struct DevPlan {
+  int Nx, N, J, M, P;
+  T L;
+  // tables, col-spec layout [J][P*P] unless noted
+  const T* twc;    // [P] cos(2 pi i / P)
+  const T* tws;    // [P] sin(2 pi i / P)
+  const T* phip;   // phi_R(b . theta'_j)                       (I_1 inner)
+  const T* Kt;     // sum_j omega_G[j][j'] phi_R(b . theta_j) / P^2 (I_1 outer)
+  const T* psi;    // psi_R(b . theta_j)                        (I_2)
+  const T* psip;   // psi_R(b . theta_j^perp)                   (I_2, I_4 inner)
+  const T* psiw;   // (pi/J) psi_R(b . theta_j) / P^2           (I_4 outer)
+  const T* psips;  // psi_R(b . theta_j^perp) / P^2             (I_3 multiplier)
+  const T* phx;    // [J][M][P][2] exp(i pi rho_m theta_j,x b_x / L)
+  const T* phy;    // [J][M][P][2] exp(i pi rho_m theta_j,y b_y / L)
+  const T* wm;     // [M] (pi/J) w_m
+  // work buffers
+  T* spec;   // [cells][4][2][P*P]  w_hat_mu, col spec
+  T* wP;     // [cells][5][P*P]     w_mu and f0 = 2 w0 - 1 on the P grid, row real
+  T* terms;  // [cells][8][P*P]     I_1 (3), I_4 (4), I_2 (1) real-space fields
+  T* acc;    // [cells][7][2][P*P]  spectral accumulators of the I_1 / I_4 tasks
+  T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
+  T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
+};
+
+// ------------------------------------------------------------------ helpers
+template <int P>
+__device__ __forceinline__ int centered(int k) {
+  return k < P / 2 ? k : k - P;
+}
+
+template <typename T>
+__device__ __forceinline__ void cmul(T ar, T ai, T br, T bi, T& cr, T& ci) {
+  cr = ar * br - ai * bi;
+  ci = ar * bi + ai * br;
+}
+
+// XCD-aware block order: consecutive logical tasks share an XCD (its L2).
+__device__ __forceinline__ int xcd_task(int b, int nb) {
+  if ((nb & 7) != 0) return b;
+  return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// ------------------------------------------------------------------ layout kernels
+// API complex [cells][N][N][2][2] -> Pauli state w[4][cells][N][N]
+template <typename T, typename TA>
+__global__ void k_api_to_state(const TA* __restrict__ W, T* __restrict__ w, int ncells, int N, int Nx) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = N * N;
+  if (idx >= ncells * per) return;
+  const TA* m = W + (size_t)idx * 8;  // W00 W01 W10 W11, each (re, im)
+  const TA w00r = m[0], w01r = m[2], w01i = m[3], w10r = m[4], w10i = m[5], w11r = m[6];
+  const size_t cs = (size_t)Nx * per;
+  w[idx] = (T)(0.5 * ((double)w00r + (double)w11r));
+  w[cs + idx] = (T)(0.5 * ((double)w10r + (double)w01r));
+  w[2 * cs + idx] = (T)(0.5 * ((double)w10i - (double)w01i));
+  w[3 * cs + idx] = (T)(0.5 * ((double)w00r - (double)w11r));
+}
+
+// Pauli state -> API complex
+template <typename T, typename TA>
+__global__ void k_state_to_api(const T* __restrict__ w, TA* __restrict__ W, int ncells, int N, int Nx) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = N * N;
+  if (idx >= ncells * per) return;
+  const size_t cs = (size_t)Nx * per;
+  const T a0 = w[idx], a1 = w[cs + idx], a2 = w[2 * cs + idx], a3 = w[3 * cs + idx];
+  TA* m = W + (size_t)idx * 8;
+  m[0] = (TA)(a0 + a3);
+  m[1] = (TA)0;
+  m[2] = (TA)a1;
+  m[3] = (TA)(-a2);
+  m[4] = (TA)a1;
+  m[5] = (TA)a2;
+  m[6] = (TA)(a0 - a3);
+  m[7] = (TA)0;
+}
+
+// ------------------------------------------------------------------ engine setup
+template <typename T, int P, int E>
+struct Kern {
+  using Eng = Fft2<T, P, E>;
+  static constexpr int NT = Eng::NT;
+  static constexpr int TPR = Eng::TPR;
+  static constexpr int FSZ = P * P;
+  static constexpr int LDS = Eng::LDS_SCALARS + 2 * P;
+};
+
+template <typename T, int P, int E>
+__device__ __forceinline__ void setup(Fft2<T, P, E>& eng, T* smem, const T* twc, const T* tws) {
+  T* tc = smem + Fft2<T, P, E>::LDS_SCALARS;
+  T* ts = tc + P;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) {
+    tc[i] = twc[i];
+    ts[i] = tws[i];
+  }
+  __syncthreads();
+  eng.init(smem, tc, ts);
+}
+
+// ------------------------------------------------------------------ dft_in
+// w_mu(v_n) -> w_hat_mu on Xi (Nyquist zeroed, padded to P, col spec), and the
+// trigonometric interpolants w_mu, f0 = 2 w0 - 1 on the P grid (row real).
+template <typename T, int P, int E>
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_dft_in(DevPlan<T> d, const T* __restrict__ w, int cell0) {
+  using K = Kern<T, P, E>;
+  __shared__ T smem[K::LDS];
+  Fft2<T, P, E> eng;
+  setup(eng, smem, d.twc, d.tws);
+  const int cell = cell0 + blockIdx.x;
+  const int N = P / 2;
+  const int t = threadIdx.x;
+  const size_t cs = (size_t)d.Nx * N * N;
+  const int y = eng.line;
+  T* spec = d.spec + (size_t)blockIdx.x * 4 * 2 * K::FSZ;
+  T* wP = d.wP + (size_t)blockIdx.x * 5 * K::FSZ;
+  const T inv_n2 = (T)1 / (T)(N * N);
+  #pragma unroll 1
+  for (int mu = 0; mu < 4; ++mu) {
+    T zr[E], zi[E];
+#pragma unroll
+    for (int n = 0; n < E; ++n) {
+      const int x = eng.sx(n);
+      T v = 0;
+      if (((x | y) & 1) == 0) {
+        const int i = centered<P>(x) / 2 + N / 2;
+        const int j = centered<P>(y) / 2 + N / 2;
+        v = w[mu * cs + ((size_t)cell * N + i) * N + j];
+      }
+      zr[n] = v;
+      zi[n] = 0;
+    }
+    eng.fwd2(zr, zi);
+    const int bx = centered<P>(eng.line);
+    const bool kx_in = bx > -N / 2 && bx < N / 2;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int by = centered<P>(eng.bk(k));
+      const bool in = kx_in && by > -N / 2 && by < N / 2;
+      spec[(mu * 2) * K::FSZ + k * K::NT + t] = in ? zr[k] * inv_n2 : (T)0;
+      spec[(mu * 2 + 1) * K::FSZ + k * K::NT + t] = in ? zi[k] * inv_n2 : (T)0;
+    }
+  }
+  #pragma unroll 1
+  for (int pr = 0; pr < 2; ++pr) {
+    T zr[E], zi[E];
+    const T* sa = spec + (2 * pr) * 2 * K::FSZ;
+    const T* sb = spec + (2 * pr + 1) * 2 * K::FSZ;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int o = k * K::NT + t;
+      // (a_r + i a_i) + i (b_r + i b_i)
+      zr[k] = sa[o] - sb[K::FSZ + o];
+      zi[k] = sa[K::FSZ + o] + sb[o];
+    }
+    eng.inv2(zr, zi);
+#pragma unroll
+    for (int n = 0; n < E; ++n) {
+      wP[(2 * pr) * K::FSZ + n * K::NT + t] = zr[n];
+      wP[(2 * pr + 1) * K::FSZ + n * K::NT + t] = zi[n];
+      if (pr == 0) wP[4 * K::FSZ + n * K::NT + t] = (T)2 * zr[n] - (T)1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ I_1, I_4, I_2
+// task 0..2: I_1[f0, w_l, .] (l = task + 1), hoisted outer kernel K_j'
+// task 3..6: I_4[f0, w_g, .] (g = task - 3)
+// Both: sum_j outer_j(p) FFT( f0 * IFFT(inner_j w_hat_g) ), then one IFFT.
+// task 7   : I_2 accumulator S = sum_j (pi/J) sum_mu eta_mu
+//            IFFT(psi_j w_hat_mu) IFFT(psi'_j w_hat_mu)   (real space)
+template <typename T, int P, int E>
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
+  using K = Kern<T, P, E>;
+  __shared__ T smem[K::LDS];
+  Fft2<T, P, E> eng;
+  setup(eng, smem, d.twc, d.tws);
+  const int cell = blockIdx.x / 8;
+  const int task = blockIdx.x % 8;
+  const int t = threadIdx.x;
+  const T* spec = d.spec + (size_t)cell * 4 * 2 * K::FSZ;
+  const T* wP = d.wP + (size_t)cell * 5 * K::FSZ;
+  T* out = d.terms + ((size_t)cell * 8 + task) * K::FSZ;
+  if (task < 7) {
+    const int g = task < 3 ? task + 1 : task - 3;
+    const T* inner = task < 3 ? d.phip : d.psip;
+    const T* outer = task < 3 ? d.Kt : d.psiw;
+    const T* sg = spec + g * 2 * K::FSZ;
+    const T* f0 = wP + 4 * K::FSZ;
+    T* acc = d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ;
+    #pragma unroll 1
+    for (int j = 0; j < d.J; ++j) {
+      T zr[E], zi[E];
+      const T* in_j = inner + (size_t)j * K::FSZ;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int o = k * K::NT + t;
+        const T a = in_j[o];
+        zr[k] = sg[o] * a;
+        zi[k] = sg[K::FSZ + o] * a;
+      }
+      eng.inv2(zr, zi);
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const T f = f0[n * K::NT + t];
+        zr[n] *= f;
+        zi[n] *= f;
+      }
+      eng.fwd2(zr, zi);
+      const T* out_j = outer + (size_t)j * K::FSZ;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int o = k * K::NT + t;
+        const T a = out_j[o];
+        if (j == 0) {
+          acc[o] = a * zr[k];
+          acc[K::FSZ + o] = a * zi[k];
+        } else {
+          acc[o] += a * zr[k];
+          acc[K::FSZ + o] += a * zi[k];
+        }
+      }
+    }
+    T zr[E], zi[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int o = k * K::NT + t;
+      zr[k] = acc[o];
+      zi[k] = acc[K::FSZ + o];
+    }
+    eng.inv2(zr, zi);
+#pragma unroll
+    for (int n = 0; n < E; ++n) out[n * K::NT + t] = zr[n];
+  } else {
+    T S[E];
+#pragma unroll
+    for (int n = 0; n < E; ++n) S[n] = 0;
+    const T wj = (T)(kPi / d.J);
+    #pragma unroll 1
+    for (int j = 0; j < d.J; ++j) {
+      const T* ps = d.psi + (size_t)j * K::FSZ;
+      const T* pp = d.psip + (size_t)j * K::FSZ;
+      #pragma unroll 1
+      for (int mu = 0; mu < 4; ++mu) {
+        const T* s = spec + mu * 2 * K::FSZ;
+        T zr[E], zi[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const int o = k * K::NT + t;
+          const T ar = s[o], ai = s[K::FSZ + o], a = ps[o], b = pp[o];
+          // w_hat psi + i w_hat psi'
+          zr[k] = ar * a - ai * b;
+          zi[k] = ai * a + ar * b;
+        }
+        eng.inv2(zr, zi);
+        const T e = mu == 0 ? wj : -wj;
+#pragma unroll
+        for (int n = 0; n < E; ++n) S[n] += e * zr[n] * zi[n];
+      }
+    }
+#pragma unroll
+    for (int n = 0; n < E; ++n) out[n * K::NT + t] = S[n];
+  }
+}
+
+// ------------------------------------------------------------------ I_3
+// One workgroup per (cell, j); loops over the M Gauss-Legendre radii.
+// Per (j, m): shifted fields s_nu = IFFT(exp(i alpha_jm . b) w_hat_nu) (two
+// packed transforms), then for each nu and each pair of mu the packed
+// convolution Phi = IFFT(psi'_j FFT(w_mu s_nu)), and
+//   o_nu += (pi/J) w_m sum_mu eta_mu s_mu Phi_mu,nu.
+template <typename T, int P, int E>
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3(DevPlan<T> d, int ncells) {
+  using K = Kern<T, P, E>;
+  __shared__ T smem[K::LDS];
+  Fft2<T, P, E> eng;
+  setup(eng, smem, d.twc, d.tws);
+  const int task = xcd_task(blockIdx.x, gridDim.x);
+  const int cell = task / d.J;
+  const int j = task % d.J;
+  const int t = threadIdx.x;
+  const T* spec = d.spec + (size_t)cell * 4 * 2 * K::FSZ;
+  const T* wP = d.wP + (size_t)cell * 5 * K::FSZ;
+  T* sbuf = d.i3s + ((size_t)cell * d.J + j) * 4 * K::FSZ;
+  T* obuf = d.i3o + ((size_t)cell * d.J + j) * 4 * K::FSZ;
+  const T* mult = d.psips + (size_t)j * K::FSZ;
+  const int kx = eng.line;
+  #pragma unroll 1
+  for (int m = 0; m < d.M; ++m) {
+    const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
+    const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2;
+    const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
+    // shifted fields
+    #pragma unroll 1
+    for (int pr = 0; pr < 2; ++pr) {
+      const T* sa = spec + (2 * pr) * 2 * K::FSZ;
+      const T* sb = spec + (2 * pr + 1) * 2 * K::FSZ;
+      T zr[E], zi[E];
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int o = k * K::NT + t;
+        const int ky = eng.bk(k);
+        T er, ei;
+        cmul(pxr, pxi, py[2 * ky], py[2 * ky + 1], er, ei);
+        T ar, ai, br, bi;
+        cmul(sa[o], sa[K::FSZ + o], er, ei, ar, ai);
+        cmul(sb[o], sb[K::FSZ + o], er, ei, br, bi);
+        zr[k] = ar - bi;
+        zi[k] = ai + br;
+      }
+      eng.inv2(zr, zi);
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        sbuf[(2 * pr) * K::FSZ + n * K::NT + t] = zr[n];
+        sbuf[(2 * pr + 1) * K::FSZ + n * K::NT + t] = zi[n];
+      }
+    }
+    const T wgt = d.wm[m];
+    #pragma unroll 1
+    for (int nu = 0; nu < 4; ++nu) {
+      T tmp[E];
+#pragma unroll
+      for (int n = 0; n < E; ++n) tmp[n] = 0;
+      #pragma unroll 1
+      for (int mp = 0; mp < 2; ++mp) {
+        const int m0 = 2 * mp, m1 = 2 * mp + 1;
+        T zr[E], zi[E];
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const int o = n * K::NT + t;
+          const T s = sbuf[nu * K::FSZ + o];
+          zr[n] = wP[m0 * K::FSZ + o] * s;
+          zi[n] = wP[m1 * K::FSZ + o] * s;
+        }
+        eng.fwd2(zr, zi);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const T a = mult[k * K::NT + t];
+          zr[k] *= a;
+          zi[k] *= a;
+        }
+        eng.inv2(zr, zi);
+        const T e0 = m0 == 0 ? (T)1 : (T)-1;
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const int o = n * K::NT + t;
+          tmp[n] += e0 * sbuf[m0 * K::FSZ + o] * zr[n] - sbuf[m1 * K::FSZ + o] * zi[n];
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const int o = nu * K::FSZ + n * K::NT + t;
+        if (m == 0)
+          obuf[o] = wgt * tmp[n];
+        else
+          obuf[o] += wgt * tmp[n];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ combine
+// Assemble the real-space P-grid fields of C (Pauli components), transform,
+// keep Xi without its -N/2 rows and columns, and evaluate on the velocity
+// grid:  c[mu][cell][i][j].
+template <typename T, int P, int E>
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T* __restrict__ c, int cell0) {
+  using K = Kern<T, P, E>;
+  __shared__ T smem[K::LDS];
+  Fft2<T, P, E> eng;
+  setup(eng, smem, d.twc, d.tws);
+  const int lc = blockIdx.x;
+  const int cell = cell0 + lc;
+  const int t = threadIdx.x;
+  const int N = P / 2;
+  const T* wP = d.wP + (size_t)lc * 5 * K::FSZ;
+  const T* tr = d.terms + (size_t)lc * 8 * K::FSZ;
+  const T* o3 = d.i3o + (size_t)lc * d.J * 4 * K::FSZ;
+  const T pi = (T)kPi;
+  const size_t cs = (size_t)d.Nx * N * N;
+  #pragma unroll 1
+  for (int pr = 0; pr < 2; ++pr) {
+    T zr[E], zi[E];
+#pragma unroll
+    for (int n = 0; n < E; ++n) {
+      const int o = n * K::NT + t;
+      const T w0 = wP[o], w1 = wP[K::FSZ + o], w2 = wP[2 * K::FSZ + o], w3 = wP[3 * K::FSZ + o];
+      const T g1 = tr[o], g2 = tr[K::FSZ + o], g3 = tr[2 * K::FSZ + o];
+      const T y0 = tr[3 * K::FSZ + o], y1 = tr[4 * K::FSZ + o], y2 = tr[5 * K::FSZ + o],
+              y3 = tr[6 * K::FSZ + o];
+      const T S = tr[7 * K::FSZ + o];
+      T b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+      #pragma unroll 1
+      for (int j = 0; j < d.J; ++j) {
+        const T* oj = o3 + (size_t)j * 4 * K::FSZ + o;
+        b0 += oj[0];
+        b1 += oj[K::FSZ];
+        b2 += oj[2 * K::FSZ];
+        b3 += oj[3 * K::FSZ];
+      }
+      T r[4];
+      // C_c,k = -2 eps_klm A^G_l w_m
+      const T cc1 = -(T)2 * (g2 * w3 - g3 * w2);
+      const T cc2 = -(T)2 * (g3 * w1 - g1 * w3);
+      const T cc3 = -(T)2 * (g1 * w2 - g2 * w1);
+      r[0] = pi * ((T)2 * S * ((T)1 - w0) - (T)2 * b0 + (T)2 * (y0 * w0 - y1 * w1 - y2 * w2 - y3 * w3));
+      r[1] = cc1 + pi * (-(T)2 * S * w1 + (T)2 * b1 + (T)2 * (y0 * w1 - y1 * w0));
+      r[2] = cc2 + pi * (-(T)2 * S * w2 + (T)2 * b2 + (T)2 * (y0 * w2 - y2 * w0));
+      r[3] = cc3 + pi * (-(T)2 * S * w3 + (T)2 * b3 + (T)2 * (y0 * w3 - y3 * w0));
+      zr[n] = r[2 * pr];
+      zi[n] = r[2 * pr + 1];
+    }
+    eng.fwd2(zr, zi);
+    const int bx = centered<P>(eng.line);
+    const bool kx_in = bx > -N / 2 && bx < N / 2;
+    const T s = (T)1 / (T)(P * P);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const int by = centered<P>(eng.bk(k));
+      const bool in = kx_in && by > -N / 2 && by < N / 2;
+      zr[k] = in ? zr[k] * s : (T)0;
+      zi[k] = in ? zi[k] * s : (T)0;
+    }
+    eng.inv2(zr, zi);
+    const int y = eng.line;
+#pragma unroll
+    for (int n = 0; n < E; ++n) {
+      const int x = eng.sx(n);
+      if (((x | y) & 1) == 0) {
+        const int i = centered<P>(x) / 2 + N / 2;
+        const int jj = centered<P>(y) / 2 + N / 2;
+        const size_t idx = ((size_t)cell * N + i) * N + jj;
+        c[(2 * pr) * cs + idx] = zr[n];
+        c[(2 * pr + 1) * cs + idx] = zi[n];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Heun stage
+// stage 1: w1 = w + dt (c + 2 B x w);  stage 2: w = (w + w1 + dt (c + 2 B x w1)) / 2
+template <typename T>
+__global__ void k_heun(T* __restrict__ w, T* __restrict__ w1, const T* __restrict__ c,
+                       const double* __restrict__ B, T dt, int Nx, int N, int stage) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = N * N;
+  if (idx >= Nx * per) return;
+  const int cell = idx / per;
+  const size_t cs = (size_t)Nx * per;
+  const T* src = stage == 1 ? w : w1;
+  const T a1 = src[cs + idx], a2 = src[2 * cs + idx], a3 = src[3 * cs + idx];
+  T m1 = 0, m2 = 0, m3 = 0;
+  if (B) {
+    const T B1 = (T)B[3 * cell], B2 = (T)B[3 * cell + 1], B3 = (T)B[3 * cell + 2];
+    m1 = (T)2 * (B2 * a3 - B3 * a2);
+    m2 = (T)2 * (B3 * a1 - B1 * a3);
+    m3 = (T)2 * (B1 * a2 - B2 * a1);
+  }
+  const T f[4] = {c[idx], c[cs + idx] + m1, c[2 * cs + idx] + m2, c[3 * cs + idx] + m3};
+  for (int mu = 0; mu < 4; ++mu) {
+    const size_t o = mu * cs + idx;
+    if (stage == 1)
+      w1[o] = w[o] + dt * f[mu];
+    else
+      w[o] = (T)0.5 * (w[o] + w1[o] + dt * f[mu]);
+  }
+}
+
+// ------------------------------------------------------------------ transport
+struct BcDev {
+  int kind;          // 0 periodic, 1 Dirichlet, 2 Maxwell
+  double alpha;
+  double Z;          // incoming flux of W_FD (Maxwell)
+};
+
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  return (a * b > (T)0) ? (fabs(a) <= fabs(b) ? a : b) : (T)0;
+}
+
+// Maxwell: outgoing number flux Fbar = h^2 sum_out tr W_b |v_x| of the cell
+// next to each Maxwell wall (float64), one workgroup per wall.
+template <typename T>
+__global__ void k_maxwell_flux(const T* __restrict__ w, double* __restrict__ flux, int Nx, int N, double L,
+                               int left_maxwell, int right_maxwell) {
+  const int wall = blockIdx.x;  // 0 left, 1 right
+  if ((wall == 0 && !left_maxwell) || (wall == 1 && !right_maxwell)) return;
+  const int cell = wall == 0 ? 0 : Nx - 1;
+  const double h = 2.0 * L / N;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
+    const int i = e / N;
+    const double vx = h * (i - N / 2);
+    const bool out = wall == 0 ? vx < 0 : vx > 0;
+    if (out) s += 2.0 * (double)w[((size_t)cell * N + i) * N + (e % N)] * fabs(vx);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) flux[wall] = h * h * red[0];
+}
+
+// One step of eq. slopeLimiterStep of length dt, all cells and velocities.
+// bcw: [2 walls][4][N][N] wall states (Dirichlet Phi or Maxwell W_FD).
+template <typename T>
+__global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T* __restrict__ bcw,
+                            const double* __restrict__ flux, BcDev bl, BcDev br, T dt, int Nx, int N, T L) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = N * N;
+  if (idx >= Nx * per) return;
+  const int cell = idx / per;
+  const int e = idx % per;
+  const int i = e / N;
+  const T h = (T)2 * L / (T)N;
+  const T vx = h * (T)(i - N / 2);
+  const T dx = (T)1 / (T)Nx;
+  const size_t cs = (size_t)Nx * per;
+  const bool periodic = bl.kind == 0;
+  // inflow factors per wall
+  T gval[4][5];
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int o = -2; o <= 2; ++o) {
+      int c = cell + o;
+      T v;
+      if (c >= 0 && c < Nx) {
+        v = w[mu * cs + (size_t)c * per + e];
+      } else if (periodic) {
+        c = ((c % Nx) + Nx) % Nx;
+        v = w[mu * cs + (size_t)c * per + e];
+      } else {
+        const bool left = c < 0;
+        const BcDev& bc = left ? bl : br;
+        const int adj = left ? 0 : Nx - 1;
+        const T* ws = bcw + (size_t)(left ? 0 : 1) * 4 * per + (size_t)mu * per;
+        bool inflow = left ? (vx > (T)0) : (vx < (T)0);
+        if (bc.kind == 2 && !left && i == 0) inflow = false;  // v_x = -L: no mirror
+        if (!inflow) {
+          v = w[mu * cs + (size_t)adj * per + e];
+        } else if (bc.kind == 1) {
+          v = ws[e];
+        } else {
+          const int mi = N - i;  // mirrored v_x row
+          const T wb = w[mu * cs + (size_t)adj * per + (size_t)mi * N + (e % N)];
+          const double fz = flux[left ? 0 : 1] / bc.Z;
+          v = (T)(1.0 - bc.alpha) * wb + (T)(bc.alpha * fz) * ws[e];
+        }
+      }
+      gval[mu][o + 2] = v;
+    }
+  }
+  const T nu = dt * vx / dx;
+  const T sg = vx > (T)0 ? (T)1 : (vx < (T)0 ? (T)-1 : (T)0);
+  const T lim = (T)0.5 * (sg - nu);
+  const T av = fabs(vx);
+  for (int mu = 0; mu < 4; ++mu) {
+    const T* g = gval[mu];
+    const T Sm = minmod(g[2] - g[1], g[1] - g[0]);
+    const T S0 = minmod(g[3] - g[2], g[2] - g[1]);
+    const T Sp = minmod(g[4] - g[3], g[3] - g[2]);
+    const T upd = -vx * (g[3] - g[1]) + av * (g[3] - (T)2 * g[2] + g[1]) +
+                  lim * (-vx * (Sp - Sm) + av * (Sp - (T)2 * S0 + Sm));
+    wn[mu * cs + idx] = g[2] + dt / ((T)2 * dx) * upd;
+  }
+}
+
+// ------------------------------------------------------------------ moments
+template <typename T>
+__global__ void k_moments(const T* __restrict__ w, double* __restrict__ mom, int Nx, int N, double L) {
+  const int cell = blockIdx.x;
+  const int per = N * N;
+  const size_t cs = (size_t)Nx * per;
+  const double h = 2.0 * L / N;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < per; e += blockDim.x) {
+    const double vx = h * (e / N - N / 2), vy = h * (e % N - N / 2);
+    const size_t o = (size_t)cell * per + e;
+    const double a0 = (double)w[o];
+    acc[0] += a0;
+    acc[1] += (double)w[cs + o];
+    acc[2] += (double)w[2 * cs + o];
+    acc[3] += (double)w[3 * cs + o];
+    acc[4] += vx * 2.0 * a0;
+    acc[5] += vy * 2.0 * a0;
+    acc[6] += 0.5 * (vx * vx + vy * vy) * 2.0 * a0;
+  }
+  __shared__ double red[7][256];
+  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < 7; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) mom[(size_t)cell * 7 + threadIdx.x] = h * h * red[threadIdx.x][0];
+}
+
+}  // namespace qb

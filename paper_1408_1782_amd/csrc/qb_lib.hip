@@ -1,0 +1,540 @@
+// Host side of the solver: plan creation (quadrature tables of Sec. 3.2,
+// device buffers), kernel launch sequences and the C ABI declared in qb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qb.h"
+#include "qb_kernels.hpp"
+
+using qb::DevPlan;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+// ------------------------------------------------------------------ quadrature (host, float64)
+// phi_R(x) = int_0^R sin(pi x r / L) dr = (2L/(pi x)) sin^2(pi R x / (2L)), phi_R(0) = 0
+double phi_R(double x, double L, double R) {
+  if (x == 0.0) return 0.0;
+  const double s = std::sin(M_PI * R * x / (2.0 * L));
+  return 2.0 * L / (M_PI * x) * s * s;
+}
+// psi_R(x) = int_{-R}^{R} exp(i pi x r / L) dr = (2L/(pi x)) sin(pi R x / L), psi_R(0) = 2R
+double psi_R(double x, double L, double R) {
+  if (x == 0.0) return 2.0 * R;
+  return 2.0 * L / (M_PI * x) * std::sin(M_PI * R * x / L);
+}
+
+// Gauss-Legendre nodes / weights on [-1, 1] by Newton iteration on P_M.
+void gauss_legendre(int M, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(M, 0.0);
+  w.assign(M, 0.0);
+  for (int i = 0; i < M; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (M + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= M; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      double pm = M == 1 ? z : p1, pm1 = M == 1 ? 1.0 : p0;
+      if (M == 1) {
+        pm = z;
+        pm1 = 1.0;
+      }
+      dp = M * (z * pm - pm1) / (z * z - 1.0);
+      const double dz = pm / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute derivative at the converged node
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= M; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double pm = M == 1 ? z : p1, pm1 = M == 1 ? 1.0 : p0;
+    dp = M * (z * pm - pm1) / (z * z - 1.0);
+    x[i] = -z;  // ascending order
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// elements per thread of the FFT engine; must match qb::Cfg used by the kernels
+int cfg_E(int precision, int P) {
+  if (precision == QB_F64) return P == 32 ? qb::Cfg<double, 32>::E : (P == 64 ? qb::Cfg<double, 64>::E : qb::Cfg<double, 128>::E);
+  return P == 32 ? qb::Cfg<float, 32>::E : (P == 64 ? qb::Cfg<float, 64>::E : qb::Cfg<float, 128>::E);
+}
+
+}  // namespace
+
+struct qb_plan_s {
+  qb_problem prob;
+  int P, E, NT, TPR;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  void *twc, *tws, *phip, *Kt, *psi, *psip, *psiw, *psips, *phx, *phy, *wm;
+  void *spec, *wP, *terms, *acc, *i3s, *i3o;
+  void *st0, *st1, *st2, *cbuf, *bcw;
+  double* flux;
+  qb::BcDev bl, br;
+
+  bool alloc(void** p, size_t n) {
+    if (!hip_ok(hipMalloc(p, n), "hipMalloc")) return false;
+    allocs.push_back(*p);
+    bytes += n;
+    return true;
+  }
+  ~qb_plan_s() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+template <typename T>
+bool upload(qb_plan_s* pl, void** dst, const std::vector<double>& v) {
+  std::vector<T> h(v.size());
+  for (size_t i = 0; i < v.size(); ++i) h[i] = (T)v[i];
+  if (!pl->alloc(dst, h.size() * sizeof(T))) return false;
+  return hip_ok(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+}
+
+// col spec position of frequency indices (kx, ky) (FFT order)
+inline size_t colspec_index(int kx, int ky, int E, int TPR, int NT) {
+  const int lb = qb::ilog2(TPR);
+  const int q = qb::bitrev_rt(ky / E, lb);
+  const int t = kx * TPR + q;
+  return (size_t)(ky % E) * NT + t;
+}
+
+inline int centered_h(int k, int P) { return k < P / 2 ? k : k - P; }
+
+template <typename T>
+bool build_tables(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  const int P = pl->P, E = pl->E, NT = pl->NT, TPR = pl->TPR, J = p.J, M = p.M;
+  const double L = p.L, R = p.R;
+  const size_t FSZ = (size_t)P * P;
+  std::vector<double> twc(P), tws(P);
+  for (int i = 0; i < P; ++i) {
+    twc[i] = std::cos(2.0 * M_PI * i / P);
+    tws[i] = std::sin(2.0 * M_PI * i / P);
+  }
+  std::vector<double> th_c(J), th_s(J), thp_c(J), thp_s(J);
+  for (int j = 0; j < J; ++j) {
+    th_c[j] = std::cos(j * M_PI / J);
+    th_s[j] = std::sin(j * M_PI / J);
+    thp_c[j] = std::cos((j + 0.5) * M_PI / J);
+    thp_s[j] = std::sin((j + 0.5) * M_PI / J);
+  }
+  // omega_G[j][j'] = -(2 pi / J)^2 / (theta_j . theta'_j')   (eq. approxG)
+  std::vector<double> wG((size_t)J * J);
+  for (int j = 0; j < J; ++j)
+    for (int jp = 0; jp < J; ++jp)
+      wG[(size_t)j * J + jp] = -std::pow(2.0 * M_PI / J, 2) / (th_c[j] * thp_c[jp] + th_s[j] * thp_s[jp]);
+  const double invP2 = 1.0 / ((double)P * P);
+  std::vector<double> phip(J * FSZ), Kt(J * FSZ), psi(J * FSZ), psip(J * FSZ), psiw(J * FSZ),
+      psips(J * FSZ);
+  std::vector<double> phi_j(J);
+  for (int kx = 0; kx < P; ++kx) {
+    const double bx = centered_h(kx, P);
+    for (int ky = 0; ky < P; ++ky) {
+      const double by = centered_h(ky, P);
+      const size_t o = colspec_index(kx, ky, E, TPR, NT);
+      for (int j = 0; j < J; ++j) phi_j[j] = phi_R(bx * th_c[j] + by * th_s[j], L, R);
+      for (int j = 0; j < J; ++j) {
+        phip[j * FSZ + o] = phi_R(bx * thp_c[j] + by * thp_s[j], L, R);
+        double k = 0.0;
+        for (int i = 0; i < J; ++i) k += wG[(size_t)i * J + j] * phi_j[i];
+        Kt[j * FSZ + o] = k * invP2;
+        const double ps = psi_R(bx * th_c[j] + by * th_s[j], L, R);
+        const double pp = psi_R(-bx * th_s[j] + by * th_c[j], L, R);  // theta_j rotated by pi/2
+        psi[j * FSZ + o] = ps;
+        psip[j * FSZ + o] = pp;
+        psiw[j * FSZ + o] = (M_PI / J) * ps * invP2;
+        psips[j * FSZ + o] = pp * invP2;
+      }
+    }
+  }
+  std::vector<double> gx, gw;
+  gauss_legendre(M, gx, gw);
+  std::vector<double> phx((size_t)J * M * P * 2), phy((size_t)J * M * P * 2), wm(M);
+  for (int m = 0; m < M; ++m) wm[m] = (M_PI / J) * R * gw[m];
+  for (int j = 0; j < J; ++j)
+    for (int m = 0; m < M; ++m) {
+      const double rho = R * gx[m];
+      for (int k = 0; k < P; ++k) {
+        const double b = centered_h(k, P);
+        const double ax = M_PI * rho * th_c[j] * b / L, ay = M_PI * rho * th_s[j] * b / L;
+        const size_t o = (((size_t)j * M + m) * P + k) * 2;
+        phx[o] = std::cos(ax);
+        phx[o + 1] = std::sin(ax);
+        phy[o] = std::cos(ay);
+        phy[o + 1] = std::sin(ay);
+      }
+    }
+  return upload<T>(pl, &pl->twc, twc) && upload<T>(pl, &pl->tws, tws) && upload<T>(pl, &pl->phip, phip) &&
+         upload<T>(pl, &pl->Kt, Kt) && upload<T>(pl, &pl->psi, psi) && upload<T>(pl, &pl->psip, psip) &&
+         upload<T>(pl, &pl->psiw, psiw) && upload<T>(pl, &pl->psips, psips) && upload<T>(pl, &pl->phx, phx) &&
+         upload<T>(pl, &pl->phy, phy) && upload<T>(pl, &pl->wm, wm);
+}
+
+// Pauli components of W_FD (eq. W_FermiDirac) on the velocity grid: [4][N][N]
+void fd_pauli(const qb_fd& s, int N, double L, double* out) {
+  const double h = 2.0 * L / N;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      const double vx = h * (i - N / 2), vy = h * (j - N / 2);
+      const double om = 0.5 * (vx * vx + vy * vy);
+      const double fu = 1.0 / (std::exp((om - s.mu_up) * s.inv_kT) + 1.0);
+      const double fd = 1.0 / (std::exp((om - s.mu_down) * s.inv_kT) + 1.0);
+      // W = U diag(fu, fd) U^H, U row-major
+      double Wr[4], Wi[4];
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+          double re = 0, im = 0;
+          for (int c = 0; c < 2; ++c) {
+            const double f = c == 0 ? fu : fd;
+            const double ur = s.U_re[a * 2 + c], ui = s.U_im[a * 2 + c];
+            const double vr = s.U_re[b * 2 + c], vi = -s.U_im[b * 2 + c];  // conj(U[b][c])
+            re += f * (ur * vr - ui * vi);
+            im += f * (ur * vi + ui * vr);
+          }
+          Wr[a * 2 + b] = re;
+          Wi[a * 2 + b] = im;
+        }
+      const size_t o = (size_t)i * N + j, cs = (size_t)N * N;
+      out[o] = 0.5 * (Wr[0] + Wr[3]);
+      out[cs + o] = 0.5 * (Wr[2] + Wr[1]);
+      out[2 * cs + o] = 0.5 * (Wi[2] - Wi[1]);
+      out[3 * cs + o] = 0.5 * (Wr[0] - Wr[3]);
+    }
+}
+
+template <typename T>
+bool build_bc(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  const int N = p.N;
+  const size_t per = (size_t)N * N;
+  std::vector<double> bw(2 * 4 * per, 0.0);
+  const qb_bc* bcs[2] = {&p.left, &p.right};
+  qb::BcDev* dv[2] = {&pl->bl, &pl->br};
+  const double h = 2.0 * p.L / N;
+  for (int wall = 0; wall < 2; ++wall) {
+    const qb_bc& b = *bcs[wall];
+    dv[wall]->kind = b.kind;
+    dv[wall]->alpha = b.alpha;
+    dv[wall]->Z = 1.0;
+    if (b.kind == QB_PERIODIC) continue;
+    double* o = bw.data() + wall * 4 * per;
+    fd_pauli(b.state, N, p.L, o);
+    if (b.kind == QB_MAXWELL) {
+      // Z = h^2 sum over incoming (mirrored) rows of tr W_FD |v_x|
+      double Z = 0.0;
+      for (int i = 0; i < N; ++i) {
+        const double vx = h * (i - N / 2);
+        const bool in = wall == 0 ? vx > 0 : (vx < 0 && i != 0);
+        if (!in) continue;
+        for (int j = 0; j < N; ++j) Z += 2.0 * o[(size_t)i * N + j] * std::fabs(vx);
+      }
+      dv[wall]->Z = h * h * Z;
+    }
+  }
+  if (!upload<T>(pl, &pl->bcw, bw)) return false;
+  return pl->alloc((void**)&pl->flux, 2 * sizeof(double)) &&
+         hip_ok(hipMemset(pl->flux, 0, 2 * sizeof(double)), "hipMemset");
+}
+
+template <typename T>
+bool build_buffers(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  const size_t FSZ = (size_t)pl->P * pl->P, C = p.Nx, J = p.J;
+  const size_t st = (size_t)4 * C * p.N * p.N * sizeof(T);
+  return pl->alloc(&pl->spec, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->wP, C * 5 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->terms, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->acc, C * 14 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->st0, st) && pl->alloc(&pl->st1, st) && pl->alloc(&pl->st2, st) &&
+         pl->alloc(&pl->cbuf, st);
+}
+
+template <typename T>
+DevPlan<T> devplan(qb_plan_s* pl) {
+  DevPlan<T> d;
+  d.Nx = pl->prob.Nx;
+  d.N = pl->prob.N;
+  d.J = pl->prob.J;
+  d.M = pl->prob.M;
+  d.P = pl->P;
+  d.L = (T)pl->prob.L;
+  d.twc = (const T*)pl->twc;
+  d.tws = (const T*)pl->tws;
+  d.phip = (const T*)pl->phip;
+  d.Kt = (const T*)pl->Kt;
+  d.psi = (const T*)pl->psi;
+  d.psip = (const T*)pl->psip;
+  d.psiw = (const T*)pl->psiw;
+  d.psips = (const T*)pl->psips;
+  d.phx = (const T*)pl->phx;
+  d.phy = (const T*)pl->phy;
+  d.wm = (const T*)pl->wm;
+  d.spec = (T*)pl->spec;
+  d.wP = (T*)pl->wP;
+  d.terms = (T*)pl->terms;
+  d.acc = (T*)pl->acc;
+  d.i3s = (T*)pl->i3s;
+  d.i3o = (T*)pl->i3o;
+  return d;
+}
+
+// C[w] for cells [0, ncells) of the Pauli state w -> c (both [4][Nx][N][N])
+template <typename T, int P>
+bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
+  constexpr int E = qb::Cfg<T, P>::E;
+  constexpr int NT = qb::Fft2<T, P, E>::NT;
+  DevPlan<T> d = devplan<T>(pl);
+  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, 0);
+  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL((qb::k_i3<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+  hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, 0);
+  return hip_ok(hipGetLastError(), "collision launch");
+}
+
+template <typename T>
+bool collision_any(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
+  switch (pl->P) {
+    case 32: return collision_pipeline<T, 32>(pl, w, c, ncells, s);
+    case 64: return collision_pipeline<T, 64>(pl, w, c, ncells, s);
+    case 128: return collision_pipeline<T, 128>(pl, w, c, ncells, s);
+  }
+  return false;
+}
+
+int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
+
+template <typename T>
+bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)p.Nx * p.N * p.N;
+  const int lm = p.left.kind == QB_MAXWELL, rm = p.right.kind == QB_MAXWELL;
+  if (lm || rm) hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur, pl->flux, p.Nx, p.N, p.L, lm, rm);
+  hipLaunchKernelGGL((qb::k_transport<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, tmp, (const T*)pl->bcw,
+                     pl->flux, pl->bl, pl->br, (T)dt, p.Nx, p.N, (T)p.L);
+  std::swap(cur, tmp);
+  return hip_ok(hipGetLastError(), "transport launch");
+}
+
+template <typename T>
+bool moments(qb_plan_s* pl, const T* w, double* mom, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  hipLaunchKernelGGL((qb::k_moments<T>), dim3(p.Nx), dim3(256), 0, s, w, mom, p.Nx, p.N, p.L);
+  return hip_ok(hipGetLastError(), "moments launch");
+}
+
+template <typename T, typename TA>
+bool to_state(qb_plan_s* pl, const void* W, T* w, int ncells, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)ncells * p.N * p.N;
+  hipLaunchKernelGGL((qb::k_api_to_state<T, TA>), dim3(blocks(n, 256)), dim3(256), 0, s, (const TA*)W, w, ncells,
+                     p.N, p.Nx);
+  return hip_ok(hipGetLastError(), "layout launch");
+}
+template <typename T, typename TA>
+bool from_state(qb_plan_s* pl, const T* w, void* W, int ncells, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)ncells * p.N * p.N;
+  hipLaunchKernelGGL((qb::k_state_to_api<T, TA>), dim3(blocks(n, 256)), dim3(256), 0, s, w, (TA*)W, ncells, p.N,
+                     p.Nx);
+  return hip_ok(hipGetLastError(), "layout launch");
+}
+
+template <typename T>
+qb_status do_collision(qb_plan_s* pl, const void* W, void* C, int ncells, hipStream_t s) {
+  T* w = (T*)pl->st0;
+  T* c = (T*)pl->cbuf;
+  if (!to_state<T, T>(pl, W, w, ncells, s)) return QB_EHIP;
+  if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;
+  if (!from_state<T, T>(pl, c, C, ncells, s)) return QB_EHIP;
+  return QB_OK;
+}
+
+template <typename T>
+qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps, double* mom, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  T* cur = (T*)pl->st0;
+  T* tmp = (T*)pl->st2;
+  T* w1 = (T*)pl->st1;
+  T* c = (T*)pl->cbuf;
+  const size_t n = (size_t)p.Nx * p.N * p.N;
+  const size_t mstride = (size_t)p.Nx * 7;
+  if (!to_state<T, T>(pl, W, cur, p.Nx, s)) return QB_EHIP;
+  if (mom && !moments<T>(pl, cur, mom, s)) return QB_EHIP;
+  for (int it = 0; it < nsteps; ++it) {
+    if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
+    if (!collision_any<T>(pl, cur, c, p.Nx, s)) return QB_EHIP;
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 1);
+    if (!collision_any<T>(pl, w1, c, p.Nx, s)) return QB_EHIP;
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 2);
+    if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
+    if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
+    if (mom && !moments<T>(pl, cur, mom + (it + 1) * mstride, s)) return QB_EHIP;
+  }
+  if (!from_state<T, T>(pl, cur, W, p.Nx, s)) return QB_EHIP;
+  // keep st0 as the home of the state for the next call
+  if (cur != (T*)pl->st0) std::swap(pl->st0, pl->st2);
+  return QB_OK;
+}
+
+template <typename T>
+qb_status do_transport(qb_plan_s* pl, void* W, double dt, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  T* cur = (T*)pl->st0;
+  T* tmp = (T*)pl->st2;
+  if (!to_state<T, T>(pl, W, cur, p.Nx, s)) return QB_EHIP;
+  if (!transport<T>(pl, cur, tmp, dt, s)) return QB_EHIP;
+  if (!from_state<T, T>(pl, cur, W, p.Nx, s)) return QB_EHIP;
+  if (cur != (T*)pl->st0) std::swap(pl->st0, pl->st2);
+  return QB_OK;
+}
+
+template <typename T>
+qb_status do_moments(qb_plan_s* pl, const void* W, double* mom, hipStream_t s) {
+  T* cur = (T*)pl->st0;
+  if (!to_state<T, T>(pl, W, cur, pl->prob.Nx, s)) return QB_EHIP;
+  if (!moments<T>(pl, cur, mom, s)) return QB_EHIP;
+  return QB_OK;
+}
+
+qb_status validate_bc(const qb_bc& b) {
+  if (b.kind != QB_PERIODIC && b.kind != QB_DIRICHLET && b.kind != QB_MAXWELL) return QB_EINVAL;
+  if (b.kind == QB_MAXWELL && !(b.alpha >= 0.0 && b.alpha <= 1.0)) return QB_EINVAL;
+  if (b.kind != QB_PERIODIC && !(b.state.inv_kT > 0.0)) return QB_EINVAL;
+  return QB_OK;
+}
+
+qb_status validate(const qb_problem* p) {
+  if (!p) return QB_EINVAL;
+  if (p->Nx < 1 || p->J < 1 || p->M < 1 || !(p->L > 0.0) || !(p->R >= 0.0)) return QB_EINVAL;
+  if (p->precision != QB_F64 && p->precision != QB_F32) return QB_EINVAL;
+  if (p->N != 16 && p->N != 32 && p->N != 64) return QB_ENOTSUP;
+  if ((p->J % 2) != 0 || p->J > 128 || p->M > 256) return QB_ENOTSUP;
+  qb_status s = validate_bc(p->left);
+  if (s != QB_OK) return s;
+  s = validate_bc(p->right);
+  if (s != QB_OK) return s;
+  if ((p->left.kind == QB_PERIODIC) != (p->right.kind == QB_PERIODIC)) return QB_EINVAL;
+  return QB_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+qb_status qb_plan_create(const qb_problem* problem, qb_plan* out) {
+  if (!out) return QB_EINVAL;
+  *out = nullptr;
+  qb_status st = validate(problem);
+  if (st != QB_OK) return st;
+  qb_plan_s* pl = new qb_plan_s();
+  pl->prob = *problem;
+  pl->P = 2 * problem->N;
+  pl->E = cfg_E(problem->precision, pl->P);
+  pl->TPR = pl->P / pl->E;
+  pl->NT = pl->P * pl->TPR;
+  bool ok;
+  if (problem->precision == QB_F64)
+    ok = build_tables<double>(pl) && build_bc<double>(pl) && build_buffers<double>(pl);
+  else
+    ok = build_tables<float>(pl) && build_bc<float>(pl) && build_buffers<float>(pl);
+  if (!ok) {
+    delete pl;
+    return QB_EHIP;
+  }
+  *out = pl;
+  return QB_OK;
+}
+
+qb_status qb_plan_destroy(qb_plan plan) {
+  if (!plan) return QB_EINVAL;
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return QB_OK;
+}
+
+size_t qb_plan_bytes(qb_plan plan) { return plan ? plan->bytes : 0; }
+
+qb_status qb_collision(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream) {
+  if (!plan || !W || !C || W == C) return QB_EINVAL;
+  if (ncells < 1) return QB_EINVAL;
+  if (ncells > plan->prob.Nx) return QB_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_collision<double>(plan, W, C, ncells, s);
+  return do_collision<float>(plan, W, C, ncells, s);
+}
+
+static qb_status check_cfl(qb_plan plan, double dt) {
+  const qb_problem& p = plan->prob;
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return QB_EINVAL;
+  const double vmax = p.L;  // |v_x| <= L on the grid (row v_x = -L)
+  if (dt * vmax * p.Nx > 1.0 + 1e-12) return QB_ECFL;
+  return QB_OK;
+}
+
+qb_status qb_transport_step(qb_plan plan, void* W, double dt, void* stream) {
+  if (!plan || !W) return QB_EINVAL;
+  qb_status st = check_cfl(plan, dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_transport<double>(plan, W, dt, s);
+  return do_transport<float>(plan, W, dt, s);
+}
+
+qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, double* moments_out,
+                  void* stream) {
+  if (!plan || !W || nsteps < 0) return QB_EINVAL;
+  qb_status st = check_cfl(plan, 0.5 * dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, moments_out, s);
+  return do_step<float>(plan, W, B, dt, nsteps, moments_out, s);
+}
+
+qb_status qb_moments(qb_plan plan, const void* W, double* mom, void* stream) {
+  if (!plan || !W || !mom) return QB_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_moments<double>(plan, W, mom, s);
+  return do_moments<float>(plan, W, mom, s);
+}
+
+const char* qb_strerror(qb_status status) {
+  switch (status) {
+    case QB_OK: return "ok";
+    case QB_EINVAL: return "invalid argument";
+    case QB_ENOTSUP: return "unsupported problem size (N must be 16, 32 or 64; J even)";
+    case QB_ECFL: return "CFL condition violated: dt max|v_x| / dx > 1";
+    case QB_EWORKSPACE: return "more cells than the plan holds";
+    case QB_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* qb_last_error(void) { return g_last_error.c_str(); }
+
+int32_t qb_version(void) { return 100; }
+
+}  // extern "C"
