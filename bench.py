@@ -1,0 +1,177 @@
+#!/usr/bin/env python
+"""Throughput of the splitting time step on the 64 x 64 velocity grid.
+
+Workload: the wall-bounded slab (Nx = 256 cells, N = 64, J = 32, M = 64,
+L = 12, R = 7.5; Dirichlet inflow on the left, Maxwell wall alpha = 0.5 on
+the right; smooth seeded field B with max |B| = 1; dt = 5e-4), seeded
+synthetic initial data, float32 bulk with float64 moments, and the same
+shape in float64.  One step = transport dt/2, Heun step of C[W] + field term,
+transport dt/2, float64 moments.  The metric is cells * steps / s over the
+whole job (one GPU), timed with the state already resident in HBM.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "cells*steps/s at 64x64 momentum grid (FP64 vs FP32); adjoint/forward time ratio"
+PEAK = {"f32": 157.3, "f64": 78.6}   # TFLOP/s, MI355X vector (fp32 figure assumes packed math)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def i3_flops(ncells, N, J, M):
+    """Algorithmic flops of one I_3 launch: per (cell, j, m) 18 complex
+    2N x 2N transforms (2 packed shift transforms + 8 packed convolutions of
+    two transforms each), 5 n log2 n flops per transform of n = (2N)^2 points."""
+    P = 2 * N
+    n = P * P
+    return ncells * J * M * 18 * 5.0 * n * math.log2(n)
+
+
+def run_gpu(wl, precision, steps, warmup):
+    import torch
+    import paper_1408_1782_amd as qb
+
+    cdt = torch.complex64 if precision == "f32" else torch.complex128
+    prob = qb.Problem(wl.Nx, wl.N, wl.J, wl.M, wl.L, wl.R, precision,
+                      qb.BC.from_workload(wl.left), qb.BC.from_workload(wl.right))
+    plan = qb.Plan(prob)
+    W = torch.from_numpy(wl.W0).to(cdt).cuda().contiguous()
+    B = torch.from_numpy(wl.B).cuda().contiguous()
+    mom = torch.zeros((steps + 1, wl.Nx, 7), dtype=torch.float64, device="cuda")
+    if warmup > 0:
+        log(f"[{precision}] warmup {warmup} step(s)")
+        plan.step(W, B, wl.dt, warmup, torch.zeros((warmup + 1, wl.Nx, 7), dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+    plan.profile(True)
+    for k in qb._lib.KERNELS:
+        plan.profile_read(k)     # discard anything recorded before
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.step(W, B, wl.dt, steps, mom)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"[{precision}] {steps} step(s) in {t1 - t0:.3f} s")
+    kern = {k: plan.profile_read(k) for k in qb._lib.KERNELS}
+    plan.profile(False)
+    m = mom.cpu().numpy()
+    tot0, tot1 = m[0].sum(0), m[-1].sum(0)
+    plan.close()
+    return t1 - t0, kern, tot0, tot1
+
+
+def cpu_baseline(wl):
+    """The CPU oracle on a bounded sample of the same workload: one collision
+    evaluation of one cell plus one transport half-step over all cells."""
+    import numpy as np
+    from oracle import collision as oc
+    from oracle import pauli
+    from oracle import transport as tp
+    from oracle.fermi_dirac import fd_matrix
+
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    w = pauli.to_pauli(wl.W0)
+    t = oc.Tables(wl.N, wl.L, wl.R, wl.J, wl.M)
+    t0 = time.perf_counter()
+    oc.collision_pauli(w[0], wl.L, wl.R, wl.J, wl.M, t)
+    t_eval = time.perf_counter() - t0
+    v = (2 * wl.L / wl.N) * (np.arange(wl.N) - wl.N // 2)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    def bc(b):
+        if b.kind == "periodic":
+            return {"kind": "periodic"}
+        st = pauli.to_pauli(fd_matrix(vx, vy, b.inv_kT, b.mu_up, b.mu_down, b.U))
+        return {"kind": b.kind, "state": st, "alpha": b.alpha}
+    t0 = time.perf_counter()
+    tp.transport_step(w, 0.5 * wl.dt, bc(wl.left), bc(wl.right), wl.L)
+    t_tr = (time.perf_counter() - t0) / wl.Nx
+    rate = 1.0 / (2 * t_eval + 2 * t_tr)
+    return {
+        "value": rate,
+        "unit": "cells*steps/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"1 cell x 1 collision evaluation (N={wl.N}, J={wl.J}, M={wl.M}, "
+                   f"{t_eval:.1f} s) + 1 transport half-step over {wl.Nx} cells; "
+                   "rate = 1 / (2 t_eval + 2 t_transport_per_cell)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-f64", action="store_true", help="skip the float64 run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--nx", type=int, default=None, help="fewer cells (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import workloads
+
+    wl = workloads.config(3, Nx=args.nx)
+    log(f"workload {wl.name}: Nx={wl.Nx} N={wl.N} J={wl.J} M={wl.M} dt={wl.dt}")
+    t32, k32, a32, b32 = run_gpu(wl, "f32", args.steps, args.warmup)
+    out = {
+        "metric": METRIC,
+        "value": wl.Nx * args.steps / t32,
+        "unit": "cells*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "dirichlet_maxwell_slab", "Nx": wl.Nx, "N": wl.N, "J": wl.J, "M": wl.M,
+                   "L": wl.L, "R": wl.R, "dt": wl.dt, "bc": "dirichlet|maxwell(alpha=0.5)",
+                   "moments": "f64"},
+    }
+
+    def roof(kern, precision):
+        ms, n = kern["i3"]
+        avg_s = ms / max(n, 1) / 1e3
+        ach = i3_flops(wl.Nx, wl.N, wl.J, wl.M) / avg_s / 1e12
+        return {"kernel": "k_i3", "bound": "alu", "achieved": ach, "peak": PEAK[precision],
+                "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": None,
+                "avg_launch_ms": ms / max(n, 1), "launches": n}
+
+    out["roofline"] = roof(k32, "f32")
+    out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in k32.items()}
+    drift = lambda a, b: {"density": float((b[0] - a[0]) / a[0]), "energy": float((b[6] - a[6]) / a[6])}
+    out["moment_drift_f32"] = drift(a32, b32)
+    if not args.no_f64:
+        t64, k64, a64, b64 = run_gpu(wl, "f64", args.steps, args.warmup)
+        out["value_f64"] = wl.Nx * args.steps / t64
+        out["ms_per_step_f64"] = 1e3 * t64 / args.steps
+        out["roofline_f64"] = roof(k64, "f64")
+        out["moment_drift_f64"] = drift(a64, b64)
+    out["adjoint_forward_ratio"] = None
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

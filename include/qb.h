@@ -136,6 +136,24 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 /* float64 moments [Nx][7] of W ([Nx][N][N][2][2] complex). */
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
+/* Kernel timing.  With profiling on, every kernel the plan launches is
+ * bracketed by a pair of HIP events on its stream; qb_profile_read
+ * synchronizes those events and returns, for one kernel class, the summed
+ * duration in milliseconds and the number of launches since the last read
+ * (then resets that class).  Profiling adds two event records per launch. */
+typedef enum {
+  QB_K_DFT_IN = 0,  /* velocity grid -> Fourier coefficients, padded-grid interpolants */
+  QB_K_TERMS = 1,   /* I_1 (kernel G), I_4 and I_2 (kernel H_J) */
+  QB_K_I3 = 2,      /* I_3 (kernel H_JM), the dominant kernel */
+  QB_K_COMBINE = 3, /* Pauli assembly, final transform, output on the grid */
+  QB_K_TRANSPORT = 4,
+  QB_K_HEUN = 5,
+  QB_K_MOMENTS = 6,
+  QB_K_COUNT = 7
+} qb_kernel;
+qb_status qb_profile(qb_plan plan, int32_t enable);
+qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_t* launches);
+
 /* Human-readable name of a status; text of the last HIP error seen. */
 const char* qb_strerror(qb_status status);
 const char* qb_last_error(void);

@@ -15,6 +15,7 @@ QB_OK, QB_EINVAL, QB_ENOTSUP, QB_ECFL, QB_EWORKSPACE, QB_EHIP = 0, -1, -2, -3, -
 QB_F64, QB_F32 = 0, 1
 QB_PERIODIC, QB_DIRICHLET, QB_MAXWELL = 0, 1, 2
 _KINDS = {"periodic": QB_PERIODIC, "dirichlet": QB_DIRICHLET, "maxwell": QB_MAXWELL}
+KERNELS = {"dft_in": 0, "terms": 1, "i3": 2, "combine": 3, "transport": 4, "heun": 5, "moments": 6}
 
 # names the header declares (checked by the CPU tests)
 EXPORTS = (
@@ -25,6 +26,8 @@ EXPORTS = (
     "qb_transport_step",
     "qb_step",
     "qb_moments",
+    "qb_profile",
+    "qb_profile_read",
     "qb_strerror",
     "qb_last_error",
     "qb_version",
@@ -91,6 +94,10 @@ def _declare(lib):
     lib.qb_step.restype = i32
     lib.qb_moments.argtypes = [vp, vp, vp, vp]
     lib.qb_moments.restype = i32
+    lib.qb_profile.argtypes = [vp, i32]
+    lib.qb_profile.restype = i32
+    lib.qb_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
+    lib.qb_profile_read.restype = i32
     lib.qb_strerror.argtypes = [i32]
     lib.qb_strerror.restype = ctypes.c_char_p
     lib.qb_last_error.argtypes = []
@@ -257,6 +264,18 @@ class Plan:
             out = torch.empty((self.problem.Nx, 7), dtype=torch.float64, device=W.device)
         _check(self.lib.qb_moments(self.handle, _ptr(W), _ptr(out), _stream()), "qb_moments")
         return out
+
+    def profile(self, enable=True):
+        """qb_profile: bracket every launch of this plan with HIP events."""
+        _check(self.lib.qb_profile(self.handle, 1 if enable else 0), "qb_profile")
+
+    def profile_read(self, kernel):
+        """qb_profile_read: (total ms, launches) of one kernel class since the last read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.qb_profile_read(self.handle, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)),
+               "qb_profile_read")
+        return ms.value, n.value
 
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:

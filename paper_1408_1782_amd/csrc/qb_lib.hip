@@ -92,6 +92,14 @@ struct qb_plan_s {
   void *st0, *st1, *st2, *cbuf, *bcw;
   double* flux;
   qb::BcDev bl, br;
+  // kernel timing
+  bool profiling = false;
+  struct Rec {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
 
   bool alloc(void** p, size_t n) {
     if (!hip_ok(hipMalloc(p, n), "hipMalloc")) return false;
@@ -100,7 +108,33 @@ struct qb_plan_s {
     return true;
   }
   ~qb_plan_s() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
+  }
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  // bracket one launch: call begin() before and end() after the launch
+  int begin(int kernel, hipStream_t s) {
+    if (!profiling) return -1;
+    Rec r{kernel, event(), event()};
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t s) {
+    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
   }
 };
 
@@ -307,10 +341,18 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t
   constexpr int E = qb::Cfg<T, P>::E;
   constexpr int NT = qb::Fft2<T, P, E>::NT;
   DevPlan<T> d = devplan<T>(pl);
+  int id = pl->begin(QB_K_DFT_IN, s);
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, 0);
+  pl->end(id, s);
+  id = pl->begin(QB_K_TERMS, s);
   hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  pl->end(id, s);
+  id = pl->begin(QB_K_I3, s);
   hipLaunchKernelGGL((qb::k_i3<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+  pl->end(id, s);
+  id = pl->begin(QB_K_COMBINE, s);
   hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, 0);
+  pl->end(id, s);
   return hip_ok(hipGetLastError(), "collision launch");
 }
 
@@ -331,9 +373,11 @@ bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
   const qb_problem& p = pl->prob;
   const size_t n = (size_t)p.Nx * p.N * p.N;
   const int lm = p.left.kind == QB_MAXWELL, rm = p.right.kind == QB_MAXWELL;
+  const int id = pl->begin(QB_K_TRANSPORT, s);
   if (lm || rm) hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur, pl->flux, p.Nx, p.N, p.L, lm, rm);
   hipLaunchKernelGGL((qb::k_transport<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, tmp, (const T*)pl->bcw,
                      pl->flux, pl->bl, pl->br, (T)dt, p.Nx, p.N, (T)p.L);
+  pl->end(id, s);
   std::swap(cur, tmp);
   return hip_ok(hipGetLastError(), "transport launch");
 }
@@ -341,7 +385,9 @@ bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
 template <typename T>
 bool moments(qb_plan_s* pl, const T* w, double* mom, hipStream_t s) {
   const qb_problem& p = pl->prob;
+  const int id = pl->begin(QB_K_MOMENTS, s);
   hipLaunchKernelGGL((qb::k_moments<T>), dim3(p.Nx), dim3(256), 0, s, w, mom, p.Nx, p.N, p.L);
+  pl->end(id, s);
   return hip_ok(hipGetLastError(), "moments launch");
 }
 
@@ -386,9 +432,13 @@ qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps
   for (int it = 0; it < nsteps; ++it) {
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     if (!collision_any<T>(pl, cur, c, p.Nx, s)) return QB_EHIP;
+    int id = pl->begin(QB_K_HEUN, s);
     hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 1);
+    pl->end(id, s);
     if (!collision_any<T>(pl, w1, c, p.Nx, s)) return QB_EHIP;
+    id = pl->begin(QB_K_HEUN, s);
     hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 2);
+    pl->end(id, s);
     if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     if (mom && !moments<T>(pl, cur, mom + (it + 1) * mstride, s)) return QB_EHIP;
@@ -534,6 +584,36 @@ const char* qb_strerror(qb_status status) {
 }
 
 const char* qb_last_error(void) { return g_last_error.c_str(); }
+
+qb_status qb_profile(qb_plan plan, int32_t enable) {
+  if (!plan) return QB_EINVAL;
+  plan->profiling = enable != 0;
+  return QB_OK;
+}
+
+qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!plan || !total_ms || !launches || kernel < 0 || kernel >= QB_K_COUNT) return QB_EINVAL;
+  double ms = 0.0;
+  int64_t n = 0;
+  std::vector<qb_plan_s::Rec> keep;
+  for (auto& r : plan->recs) {
+    if (r.kernel != kernel) {
+      keep.push_back(r);
+      continue;
+    }
+    if (!hip_ok(hipEventSynchronize(r.b), "hipEventSynchronize")) return QB_EHIP;
+    float e = 0.f;
+    if (!hip_ok(hipEventElapsedTime(&e, r.a, r.b), "hipEventElapsedTime")) return QB_EHIP;
+    ms += e;
+    ++n;
+    plan->pool.push_back(r.a);
+    plan->pool.push_back(r.b);
+  }
+  plan->recs.swap(keep);
+  *total_ms = ms;
+  *launches = n;
+  return QB_OK;
+}
 
 int32_t qb_version(void) { return 100; }
 

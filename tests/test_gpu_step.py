@@ -1,0 +1,175 @@
+"""GPU parity of transport, the splitting step and the moments (Sec. 4,
+Sec. 2 boundary conditions) against the CPU oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import collision as oc
+from oracle import pauli
+from oracle import step as ostep
+from oracle import transport as tp
+from oracle.fermi_dirac import fd_matrix
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def bc_dict(b, N, L):
+    if b.kind == "periodic":
+        return {"kind": "periodic"}
+    v = (2 * L / N) * (np.arange(N) - N // 2)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    st = pauli.to_pauli(fd_matrix(vx, vy, b.inv_kT, b.mu_up, b.mu_down, b.U))
+    return {"kind": b.kind, "state": st, "alpha": b.alpha}
+
+
+def make_plan(w, precision, J=None, M=None):
+    import paper_1408_1782_amd as qb
+    return qb.Plan(qb.Problem(w.Nx, w.N, J or w.J, M or w.M, w.L, w.R, precision,
+                              qb.BC.from_workload(w.left), qb.BC.from_workload(w.right)))
+
+
+def to_dev(W, precision):
+    import torch
+    dt = torch.complex128 if precision == "f64" else torch.complex64
+    return torch.from_numpy(W).to(dt).cuda().contiguous()
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
+TOL = {"f64": 1e-11, "f32": 2e-5}
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_transport_matches_oracle(cfg, precision):
+    """eq. slopeLimiterStep with periodic (configuration 2) and Dirichlet /
+    Maxwell walls (configuration 3), several steps at CFL ~ 0.7."""
+    import torch
+    w = wl.config(cfg, Nx=24, N=16)
+    plan = make_plan(w, precision, J=4, M=4)
+    Wd = to_dev(w.W0, precision)
+    s = pauli.to_pauli(w.W0)
+    bl, br = bc_dict(w.left, w.N, w.L), bc_dict(w.right, w.N, w.L)
+    dt = 0.7 / (w.L * w.Nx)
+    for _ in range(5):
+        plan.transport_step(Wd, dt)
+        s = tp.transport_step(s, dt, bl, br, w.L)
+    torch.cuda.synchronize()
+    got = pauli.to_pauli(Wd.cpu().numpy().astype(np.complex128))
+    assert rel(got, s) < TOL[precision]
+    plan.close()
+
+
+def test_transport_rejects_cfl_violation():
+    import paper_1408_1782_amd as qb
+    w = wl.config(2, Nx=16, N=16)
+    plan = make_plan(w, "f64", J=4, M=4)
+    Wd = to_dev(w.W0, "f64")
+    with pytest.raises(qb.QBError) as e:
+        plan.transport_step(Wd, 1.01 / (w.L * w.Nx))
+    assert e.value.status == qb._lib.QB_ECFL
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_step_matches_oracle(cfg, precision):
+    """Full splitting step (transport, Heun with C + field, transport) and
+    float64 moments on reduced grids of configurations 2 and 3."""
+    import torch
+    w = wl.config(cfg, Nx=6, N=16)
+    J, M = 6, 6
+    plan = make_plan(w, precision, J=J, M=M)
+    Wd = to_dev(w.W0, precision)
+    B = torch.from_numpy(w.B).cuda().contiguous()
+    steps = 2
+    mom = torch.zeros((steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda")
+    plan.step(Wd, B, w.dt, steps, mom)
+    torch.cuda.synchronize()
+    t = oc.Tables(w.N, w.L, w.R, J, M)
+    s = pauli.to_pauli(w.W0)
+    bl, br = bc_dict(w.left, w.N, w.L), bc_dict(w.right, w.N, w.L)
+    moms = [ostep.moments(s, w.L)]
+    for _ in range(steps):
+        s = ostep.step(s, w.B, w.dt, w.L, w.R, J, M, bl, br, t)
+        moms.append(ostep.moments(s, w.L))
+    got = pauli.to_pauli(Wd.cpu().numpy().astype(np.complex128))
+    assert rel(got, s) < TOL[precision]
+    gm = mom.cpu().numpy()
+    assert rel(gm, np.stack(moms)) < (1e-12 if precision == "f64" else 1e-6)
+    plan.close()
+
+
+def test_moments_match_oracle():
+    import torch
+    w = wl.config(3, Nx=5, N=32)
+    plan = make_plan(w, "f64", J=4, M=4)
+    m = plan.moments(to_dev(w.W0, "f64"))
+    torch.cuda.synchronize()
+    ref = ostep.moments(pauli.to_pauli(w.W0), w.L)
+    assert rel(m.cpu().numpy(), ref) < 1e-13
+    plan.close()
+
+
+def _golden(name):
+    p = os.path.join(GOLDEN, name)
+    if not os.path.exists(p):
+        pytest.skip(f"{name} not generated (python tests/golden/make_golden.py)")
+    return np.load(p)
+
+
+def test_configuration1_full_trajectory_f64():
+    """Configuration 1 in full: 16 cells, N = 16, J = 32, M = 16, 10 steps,
+    against the stored oracle trajectory."""
+    import torch
+    g = _golden("c1_trajectory.npz")
+    w = wl.config(1)
+    plan = make_plan(w, "f64")
+    Wd = to_dev(w.W0, "f64")
+    mom = torch.zeros((w.steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda")
+    plan.step(Wd, None, w.dt, w.steps, mom)
+    torch.cuda.synchronize()
+    got = pauli.to_pauli(Wd.cpu().numpy())
+    assert rel(got, g["states"][-1]) < 1e-11
+    assert rel(mom.cpu().numpy(), g["moments"]) < 1e-12
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_configuration2_reduced_two_steps(precision):
+    """Configuration-2 recipe on 8 cells (N = 32, full quadrature, field
+    B = (0, 0, 0.5)), 2 steps, against the stored oracle states."""
+    import torch
+    g = _golden("c2_reduced.npz")
+    w = wl.config(2, Nx=8)
+    plan = make_plan(w, precision)
+    Wd = to_dev(w.W0, precision)
+    B = torch.from_numpy(w.B).cuda().contiguous()
+    plan.step(Wd, B, w.dt, 2)
+    torch.cuda.synchronize()
+    got = pauli.to_pauli(Wd.cpu().numpy().astype(np.complex128))
+    assert rel(got, g["states"][2]) < TOL[precision]
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_configuration3_sampled_cells(precision):
+    """Configuration 3 at full size (256 cells, N = 64, J = 32, M = 64), in
+    the launch configuration the benchmark times: C[W] of all cells, checked
+    at the stored oracle cells."""
+    import torch
+    g = _golden("c3_cells.npz")
+    w = wl.config(3)
+    plan = make_plan(w, precision)
+    C = plan.collision(to_dev(w.W0, precision))
+    torch.cuda.synchronize()
+    got = pauli.to_pauli(C.cpu().numpy().astype(np.complex128))
+    for k, c in enumerate(g["cells"]):
+        assert rel(got[c], g["c"][k]) < TOL[precision], c
+    plan.close()
