@@ -197,14 +197,6 @@ __device__ __forceinline__ double xor_lane(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// cos / sin of 2 pi j / m for m in {2, 4, 8}, 0 <= j < m / 2 (lane-stage twiddles)
-__device__ __forceinline__ void small_twiddle(int j, int m, double& c, double& s) {
-  const double r2 = 0.70710678118654752440084436210484904;
-  const int a = j * (8 / m);  // eighths of a turn, 0..3
-  c = a == 0 ? 1.0 : (a == 1 ? r2 : (a == 2 ? 0.0 : -r2));
-  s = a == 0 ? 0.0 : (a == 2 ? 1.0 : r2);
-}
-
 // ------------------------------------------------------------------ engine
 template <typename T, int P_, int E_>
 struct Fft2 {
@@ -213,110 +205,133 @@ struct Fft2 {
   static constexpr int TPR = P / E;
   static constexpr int NT = P * TPR;
   static constexpr int LB = ilog2(TPR);
-  static constexpr int LD = P + 1;          // padded LDS row
-  static constexpr int LDS_SCALARS = P * LD;
-  static_assert(TPR >= 1 && TPR <= 8 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2, 4 or 8");
+  // LDS transpose layout: row kx holds y at y + off(kx), rows LD apart, with
+  // off(kx) = (BW / TPR) * (kx / E), BW the number of elements per 128-byte
+  // bank cycle, LD = P + BW + TPR.  Every transpose access of a wavefront then
+  // falls into distinct banks, and each thread's E accesses differ by
+  // compile-time constants (one address register per direction).
+  static constexpr int BW = 128 / (int)sizeof(T);
+  static constexpr int LD = P + BW + TPR;
+  // The transposes can go through LDS in ROUNDS passes of P / ROUNDS kx rows
+  // each (a smaller buffer, at the price of extra barriers and registers);
+  // one pass unless QB_XPOSE_SPLIT_BYTES asks for a split.
+#ifndef QB_XPOSE_SPLIT_BYTES
+#define QB_XPOSE_SPLIT_BYTES (1 << 30)
+#endif
+  static constexpr int ROUNDS = (P * LD * (int)sizeof(T) > QB_XPOSE_SPLIT_BYTES && P / 2 >= E) ? 2 : 1;
+  static constexpr int RP = P / ROUNDS;
+  static constexpr int LDS_SCALARS = RP * LD;
+  static_assert(TPR >= 1 && TPR <= 4 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2 or 4");
   static_assert(E * TPR == P, "E * TPR must equal P");
+  static_assert(P % BW == 0, "P must be a multiple of the bank width");
 
   int t, line, q, bq;
   T* lds;          // transpose buffer, LDS_SCALARS scalars
-  const T* twc;    // LDS: cos(2 pi i / P), i < P
-  const T* tws;    // LDS: sin(2 pi i / P)
+  const T* tw;     // LDS: (cos, sin)(2 pi q k / P) at [q][k], q < TPR, k < E, row stride TWS
+  // padded row stride of the twiddle table: the TPR rows start in different banks
+  static constexpr int TWS = 2 * E + 2;
+  static constexpr int TW_SCALARS = TPR * TWS;
 
-  __device__ __forceinline__ void init(T* lds_buf, const T* tc, const T* ts) {
+  __device__ __forceinline__ void init(T* lds_buf, const T* twi) {
     t = threadIdx.x;
     line = t / TPR;
     q = t % TPR;
     bq = bitrev_rt(q, LB);
     lds = lds_buf;
-    twc = tc;
-    tws = ts;
+    tw = twi;
   }
   __device__ __forceinline__ int sx(int n) const { return q + TPR * n; }     // strided index
   __device__ __forceinline__ int bk(int k) const { return k + E * bq; }      // blocked index
+  // LDS position of (kx row inside the buffer, y) without the bank offset
+  __device__ __forceinline__ int addr(int kxl, int y) const { return kxl * LD + y; }
+  // bank offset of a kx row: spreads the TPR row groups kx / E over the banks
+  __device__ __forceinline__ int off_of(int kx) const { return (BW / TPR) * (kx / E); }
+
+  // w_P^{q k} multiply, sign SG (-1 forward, +1 inverse), k = 1..E-1
+  template <int SG>
+  __device__ __forceinline__ void twiddle(T (&zr)[E], T (&zi)[E]) const {
+    // The table is constant, so the compiler would keep all E twiddles in
+    // registers across the whole kernel; an opaque base index makes it load
+    // them where they are used instead.
+    int base = q * TWS;
+    __asm__ volatile("" : "+v"(base));
+#pragma unroll
+    for (int k = 1; k < E; ++k) {
+      const T* w = tw + base + 2 * k;
+      const T c = w[0], s = SG < 0 ? -w[1] : w[1];
+      const T r = zr[k] * c - zi[k] * s;
+      zi[k] = zr[k] * s + zi[k] * c;
+      zr[k] = r;
+    }
+  }
+
+  // Cross-lane DFT of size TPR for every k.  Forward (decimation in
+  // frequency, natural lane order in, bit-reversed out):
+  //   stage H = TPR/2 .. 1: lower lane z + o, upper lane (o - z) w_{2H}^{q mod H}
+  // For TPR <= 4 the only non-trivial stage twiddle is w_4 = -i (lane 3 of
+  // the H = 2 stage), applied as a component swap.
+  __device__ __forceinline__ void lanes_fwd(T (&zr)[E], T (&zi)[E]) const {
+    if constexpr (TPR == 4) {
+      const T sg = (q & 2) ? (T)-1 : (T)1;
+      const bool rot = q == 3;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T orr = xor_lane<2>(zr[k]), oi = xor_lane<2>(zi[k]);
+        const T dr = sg * zr[k] + orr, di = sg * zi[k] + oi;
+        zr[k] = rot ? di : dr;       // (d) * (-i) = (d_i, -d_r)
+        zi[k] = rot ? -dr : di;
+      }
+    }
+    if constexpr (TPR >= 2) {
+      const T sg = (q & 1) ? (T)-1 : (T)1;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T orr = xor_lane<1>(zr[k]), oi = xor_lane<1>(zi[k]);
+        zr[k] = sg * zr[k] + orr;
+        zi[k] = sg * zi[k] + oi;
+      }
+    }
+  }
+  // exact reverse of lanes_fwd (unnormalized: times TPR)
+  __device__ __forceinline__ void lanes_inv(T (&zr)[E], T (&zi)[E]) const {
+    if constexpr (TPR >= 2) {
+      const T sg = (q & 1) ? (T)-1 : (T)1;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T orr = xor_lane<1>(zr[k]), oi = xor_lane<1>(zi[k]);
+        zr[k] = sg * zr[k] + orr;
+        zi[k] = sg * zi[k] + oi;
+      }
+    }
+    if constexpr (TPR == 4) {
+      const T sg = (q & 2) ? (T)-1 : (T)1;
+      const bool rot = q == 3;
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        // undo the -i of lane 3: multiply by +i = (-z_i, z_r)
+        const T ar = rot ? -zi[k] : zr[k];
+        const T ai = rot ? zr[k] : zi[k];
+        const T orr = xor_lane<2>(ar), oi = xor_lane<2>(ai);
+        zr[k] = sg * ar + orr;
+        zi[k] = sg * ai + oi;
+      }
+    }
+  }
 
   // forward: strided -> blocked, exp(-2 pi i ...)
   __device__ __forceinline__ void fwd_line(T (&zr)[E], T (&zi)[E]) const {
     reg_fft<T, E, -1>(zr, zi);
     if constexpr (TPR > 1) {
-#pragma unroll
-      for (int k = 1; k < E; ++k) {
-        const int idx = (q * k) & (P - 1);
-        const T c = twc[idx], s = -tws[idx];
-        const T r = zr[k] * c - zi[k] * s;
-        zi[k] = zr[k] * s + zi[k] * c;
-        zr[k] = r;
-      }
-      lane_fwd<TPR / 2>(zr, zi);
-    }
-  }
-
-  // one radix-2 decimation-in-frequency stage across lanes q and q ^ H
-  template <int H>
-  __device__ __forceinline__ void lane_fwd(T (&zr)[E], T (&zi)[E]) const {
-    if constexpr (H >= 1) {
-      const bool upper = (q & H) != 0;
-      double cd, sd;
-      small_twiddle(q & (H - 1), 2 * H, cd, sd);
-      const T c = (T)cd, s = (T)(-sd);
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const T orr = xor_lane<H>(zr[k]);
-        const T oi = xor_lane<H>(zi[k]);
-        if (!upper) {
-          zr[k] = zr[k] + orr;
-          zi[k] = zi[k] + oi;
-        } else {
-          const T dr = orr - zr[k], di = oi - zi[k];
-          zr[k] = dr * c - di * s;
-          zi[k] = dr * s + di * c;
-        }
-      }
-      lane_fwd<H / 2>(zr, zi);
-    }
-  }
-
-  // inverse of lane_fwd<H> (times 2), stages in increasing H
-  template <int H>
-  __device__ __forceinline__ void lane_inv(T (&zr)[E], T (&zi)[E]) const {
-    if constexpr (H <= TPR / 2) {
-      const bool upper = (q & H) != 0;
-      double cd, sd;
-      small_twiddle(q & (H - 1), 2 * H, cd, sd);
-      const T c = (T)cd, s = (T)sd;
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        if (upper) {
-          const T r = zr[k] * c - zi[k] * s;
-          zi[k] = zr[k] * s + zi[k] * c;
-          zr[k] = r;
-        }
-        const T orr = xor_lane<H>(zr[k]);
-        const T oi = xor_lane<H>(zi[k]);
-        if (!upper) {
-          zr[k] = zr[k] + orr;
-          zi[k] = zi[k] + oi;
-        } else {
-          zr[k] = orr - zr[k];
-          zi[k] = oi - zi[k];
-        }
-      }
-      lane_inv<H * 2>(zr, zi);
+      twiddle<-1>(zr, zi);
+      lanes_fwd(zr, zi);
     }
   }
 
   // inverse: blocked -> strided, exp(+2 pi i ...), unnormalized
   __device__ __forceinline__ void inv_line(T (&zr)[E], T (&zi)[E]) const {
     if constexpr (TPR > 1) {
-      lane_inv<1>(zr, zi);
-#pragma unroll
-      for (int k = 1; k < E; ++k) {
-        const int idx = (q * k) & (P - 1);
-        const T c = twc[idx], s = tws[idx];
-        const T r = zr[k] * c - zi[k] * s;
-        zi[k] = zr[k] * s + zi[k] * c;
-        zr[k] = r;
-      }
+      lanes_inv(zr, zi);
+      twiddle<+1>(zr, zi);
     }
     reg_fft<T, E, +1>(zr, zi);
   }
@@ -332,21 +347,62 @@ struct Fft2 {
     xpose_cs_to_rb(zi);
   }
 
+  // With ROUNDS > 1 a thread may receive its column elements in an earlier
+  // round than the one in which it hands over its row elements, so received
+  // values go to a separate array until every round is done.
   __device__ __forceinline__ void xpose_rb_to_cs(T (&z)[E]) const {
+    if constexpr (ROUNDS == 1) {
 #pragma unroll
-    for (int k = 0; k < E; ++k) lds[bk(k) * LD + line] = z[k];
-    __syncthreads();
+      for (int k = 0; k < E; ++k) lds[addr(bk(k), line) + off_of(bk(k))] = z[k];
+      __syncthreads();
 #pragma unroll
-    for (int n = 0; n < E; ++n) z[n] = lds[line * LD + sx(n)];
-    __syncthreads();
+      for (int n = 0; n < E; ++n) z[n] = lds[addr(line, sx(n)) + off_of(line)];
+      __syncthreads();
+    } else {
+      T zn[E];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        if ((E * bq) / RP == r) {
+#pragma unroll
+          for (int k = 0; k < E; ++k) lds[addr(bk(k) - r * RP, line) + off_of(bk(k))] = z[k];
+        }
+        __syncthreads();
+        if (line / RP == r) {
+#pragma unroll
+          for (int n = 0; n < E; ++n) zn[n] = lds[addr(line - r * RP, sx(n)) + off_of(line)];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int n = 0; n < E; ++n) z[n] = zn[n];
+    }
   }
   __device__ __forceinline__ void xpose_cs_to_rb(T (&z)[E]) const {
+    if constexpr (ROUNDS == 1) {
 #pragma unroll
-    for (int n = 0; n < E; ++n) lds[line * LD + sx(n)] = z[n];
-    __syncthreads();
+      for (int n = 0; n < E; ++n) lds[addr(line, sx(n)) + off_of(line)] = z[n];
+      __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) z[k] = lds[bk(k) * LD + line];
-    __syncthreads();
+      for (int k = 0; k < E; ++k) z[k] = lds[addr(bk(k), line) + off_of(bk(k))];
+      __syncthreads();
+    } else {
+      T zn[E];
+#pragma unroll
+      for (int r = 0; r < ROUNDS; ++r) {
+        if (line / RP == r) {
+#pragma unroll
+          for (int n = 0; n < E; ++n) lds[addr(line - r * RP, sx(n)) + off_of(line)] = z[n];
+        }
+        __syncthreads();
+        if ((E * bq) / RP == r) {
+#pragma unroll
+          for (int k = 0; k < E; ++k) zn[k] = lds[addr(bk(k) - r * RP, line) + off_of(bk(k))];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int k = 0; k < E; ++k) z[k] = zn[k];
+    }
   }
 
   // full 2D: row real -> column spectra

@@ -21,15 +21,15 @@ struct Cfg;
 template <>
 struct Cfg<double, 32> { static constexpr int E = 16; };
 template <>
-struct Cfg<double, 64> { static constexpr int E = 16; };
+struct Cfg<double, 64> { static constexpr int E = 32; };
 template <>
-struct Cfg<double, 128> { static constexpr int E = 16; };
+struct Cfg<double, 128> { static constexpr int E = 32; };
 template <>
 struct Cfg<float, 32> { static constexpr int E = 16; };
 template <>
-struct Cfg<float, 64> { static constexpr int E = 16; };
+struct Cfg<float, 64> { static constexpr int E = 32; };
 template <>
-struct Cfg<float, 128> { static constexpr int E = 16; };
+struct Cfg<float, 128> { static constexpr int E = 32; };
 
 // Device-side view of the plan's tables and buffers (all device pointers).
 template <typename T>
@@ -37,8 +37,7 @@ struct DevPlan {
   int Nx, N, J, M, P;
   T L;
   // tables, col-spec layout [J][P*P] unless noted
-  const T* twc;    // [P] cos(2 pi i / P)
-  const T* tws;    // [P] sin(2 pi i / P)
+  const T* tw;     // [P][2] (cos, sin)(2 pi i / P)
   const T* phip;   // phi_R(b . theta'_j)                       (I_1 inner)
   const T* Kt;     // sum_j omega_G[j][j'] phi_R(b . theta_j) / P^2 (I_1 outer)
   const T* psi;    // psi_R(b . theta_j)                        (I_2)
@@ -55,6 +54,7 @@ struct DevPlan {
   T* acc;    // [cells][7][2][P*P]  spectral accumulators of the I_1 / I_4 tasks
   T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
   T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
+  T* i3sum;  // [cells][4][P*P]     I_3 summed over j
 };
 
 // ------------------------------------------------------------------ helpers
@@ -69,10 +69,46 @@ __device__ __forceinline__ void cmul(T ar, T ai, T br, T bi, T& cr, T& ci) {
   ci = ar * bi + ai * br;
 }
 
+// Raw buffer access: one 128-bit resource per array (scalar registers), a
+// per-thread byte offset in one vector register and a uniform byte offset,
+// so the E loads of a thread need no per-element address registers.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+template <typename T>
+__device__ __forceinline__ rsrc_t mkbuf(const T* p, size_t n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, (int)(n * sizeof(T)), 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(rsrc_t r, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void bst(rsrc_t r, T v, unsigned voff, unsigned soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  } else {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+  }
+}
+
 // XCD-aware block order: consecutive logical tasks share an XCD (its L2).
 __device__ __forceinline__ int xcd_task(int b, int nb) {
   if ((nb & 7) != 0) return b;
   return (b & 7) * (nb >> 3) + (b >> 3);
+}
+
+// Velocity-grid row index of the padded-grid point x = q + TPR n (FFT order),
+// for even x: i = centered(x)/2 + N/2.  For even q the wrap at x = N falls at
+// n = N / TPR whatever q is, so the offset is affine in n with a
+// compile-time break.
+template <int P, int TPR>
+__device__ __forceinline__ int vel_index(int q, int n) {
+  constexpr int N = P / 2;
+  return q / 2 + (TPR / 2) * n + N / 2 - (n >= N / TPR ? N : 0);
 }
 
 // ------------------------------------------------------------------ layout kernels
@@ -117,19 +153,23 @@ struct Kern {
   static constexpr int NT = Eng::NT;
   static constexpr int TPR = Eng::TPR;
   static constexpr int FSZ = P * P;
-  static constexpr int LDS = Eng::LDS_SCALARS + 2 * P;
+  static constexpr int LDS = Eng::LDS_SCALARS + Eng::TW_SCALARS;
+  // occupancy target of the transform kernels (waves per SIMD): two
+  // workgroups per compute unit where the field is small enough
+#ifndef QB_F32_P128_WAVES
+#define QB_F32_P128_WAVES 1
+#endif
+  static constexpr int WAVES = (sizeof(T) == 4 && P == 128) ? QB_F32_P128_WAVES : 1;
 };
 
 template <typename T, int P, int E>
-__device__ __forceinline__ void setup(Fft2<T, P, E>& eng, T* smem, const T* twc, const T* tws) {
-  T* tc = smem + Fft2<T, P, E>::LDS_SCALARS;
-  T* ts = tc + P;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) {
-    tc[i] = twc[i];
-    ts[i] = tws[i];
-  }
+__device__ __forceinline__ void setup(Fft2<T, P, E>& eng, T* smem, const T* tw) {
+  using F = Fft2<T, P, E>;
+  T* t2 = smem + F::LDS_SCALARS;
+  // tw holds [q][k] rows of 2E scalars; LDS rows are TWS apart
+  for (int i = threadIdx.x; i < 2 * P; i += blockDim.x) t2[(i / (2 * E)) * F::TWS + i % (2 * E)] = tw[i];
   __syncthreads();
-  eng.init(smem, tc, ts);
+  eng.init(smem, t2);
 }
 
 // ------------------------------------------------------------------ dft_in
@@ -138,61 +178,58 @@ __device__ __forceinline__ void setup(Fft2<T, P, E>& eng, T* smem, const T* twc,
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_dft_in(DevPlan<T> d, const T* __restrict__ w, int cell0) {
   using K = Kern<T, P, E>;
+  constexpr unsigned S = sizeof(T);
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
-  setup(eng, smem, d.twc, d.tws);
+  setup(eng, smem, d.tw);
   const int cell = cell0 + blockIdx.x;
   const int N = P / 2;
-  const int t = threadIdx.x;
+  const unsigned vo = threadIdx.x * S;
   const size_t cs = (size_t)d.Nx * N * N;
   const int y = eng.line;
-  T* spec = d.spec + (size_t)blockIdx.x * 4 * 2 * K::FSZ;
-  T* wP = d.wP + (size_t)blockIdx.x * 5 * K::FSZ;
+  const rsrc_t rs = mkbuf(d.spec + (size_t)blockIdx.x * 8 * K::FSZ, 8 * K::FSZ);
+  const rsrc_t rw = mkbuf(d.wP + (size_t)blockIdx.x * 5 * K::FSZ, 5 * K::FSZ);
   const T inv_n2 = (T)1 / (T)(N * N);
-  #pragma unroll 1
+  const int bx = centered<P>(eng.line);
+  const bool kx_in = bx > -N / 2 && bx < N / 2;
+#pragma unroll 1
   for (int mu = 0; mu < 4; ++mu) {
     T zr[E], zi[E];
+    // the velocity grid sits on the even points of the padded grid
+    const bool on_grid = ((eng.q | y) & 1) == 0;
+    const T* wrow = w + mu * cs + (size_t)cell * N * N + (centered<P>(y) / 2 + N / 2);
 #pragma unroll
     for (int n = 0; n < E; ++n) {
-      const int x = eng.sx(n);
-      T v = 0;
-      if (((x | y) & 1) == 0) {
-        const int i = centered<P>(x) / 2 + N / 2;
-        const int j = centered<P>(y) / 2 + N / 2;
-        v = w[mu * cs + ((size_t)cell * N + i) * N + j];
-      }
-      zr[n] = v;
+      zr[n] = on_grid ? wrow[vel_index<P, K::TPR>(eng.q, n) * N] : (T)0;
       zi[n] = 0;
     }
     eng.fwd2(zr, zi);
-    const int bx = centered<P>(eng.line);
-    const bool kx_in = bx > -N / 2 && bx < N / 2;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int by = centered<P>(eng.bk(k));
       const bool in = kx_in && by > -N / 2 && by < N / 2;
-      spec[(mu * 2) * K::FSZ + k * K::NT + t] = in ? zr[k] * inv_n2 : (T)0;
-      spec[(mu * 2 + 1) * K::FSZ + k * K::NT + t] = in ? zi[k] * inv_n2 : (T)0;
+      bst<T>(rs, in ? zr[k] * inv_n2 : (T)0, vo, ((2 * mu) * K::FSZ + k * K::NT) * S);
+      bst<T>(rs, in ? zi[k] * inv_n2 : (T)0, vo, ((2 * mu + 1) * K::FSZ + k * K::NT) * S);
     }
   }
-  #pragma unroll 1
+#pragma unroll 1
   for (int pr = 0; pr < 2; ++pr) {
     T zr[E], zi[E];
-    const T* sa = spec + (2 * pr) * 2 * K::FSZ;
-    const T* sb = spec + (2 * pr + 1) * 2 * K::FSZ;
+    const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int o = k * K::NT + t;
+      const unsigned o = k * K::NT;
       // (a_r + i a_i) + i (b_r + i b_i)
-      zr[k] = sa[o] - sb[K::FSZ + o];
-      zi[k] = sa[K::FSZ + o] + sb[o];
+      zr[k] = bld<T>(rs, vo, (fa + o) * S) - bld<T>(rs, vo, (fb + K::FSZ + o) * S);
+      zi[k] = bld<T>(rs, vo, (fa + K::FSZ + o) * S) + bld<T>(rs, vo, (fb + o) * S);
     }
     eng.inv2(zr, zi);
 #pragma unroll
     for (int n = 0; n < E; ++n) {
-      wP[(2 * pr) * K::FSZ + n * K::NT + t] = zr[n];
-      wP[(2 * pr + 1) * K::FSZ + n * K::NT + t] = zi[n];
-      if (pr == 0) wP[4 * K::FSZ + n * K::NT + t] = (T)2 * zr[n] - (T)1;
+      const unsigned o = n * K::NT;
+      bst<T>(rw, zr[n], vo, ((2 * pr) * K::FSZ + o) * S);
+      bst<T>(rw, zi[n], vo, ((2 * pr + 1) * K::FSZ + o) * S);
+      if (pr == 0) bst<T>(rw, (T)2 * zr[n] - (T)1, vo, (4 * K::FSZ + o) * S);
     }
   }
 }
@@ -206,82 +243,84 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_dft_in(DevPlan<T> d, co
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
   using K = Kern<T, P, E>;
+  constexpr unsigned S = sizeof(T);
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
-  setup(eng, smem, d.twc, d.tws);
+  setup(eng, smem, d.tw);
   const int cell = blockIdx.x / 8;
   const int task = blockIdx.x % 8;
-  const int t = threadIdx.x;
-  const T* spec = d.spec + (size_t)cell * 4 * 2 * K::FSZ;
-  const T* wP = d.wP + (size_t)cell * 5 * K::FSZ;
-  T* out = d.terms + ((size_t)cell * 8 + task) * K::FSZ;
+  const unsigned vo = threadIdx.x * S;
+  const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
+  const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
+  const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * 8 + task) * K::FSZ, K::FSZ);
+  const size_t tabn = (size_t)d.J * K::FSZ;
   if (task < 7) {
     const int g = task < 3 ? task + 1 : task - 3;
-    const T* inner = task < 3 ? d.phip : d.psip;
-    const T* outer = task < 3 ? d.Kt : d.psiw;
-    const T* sg = spec + g * 2 * K::FSZ;
-    const T* f0 = wP + 4 * K::FSZ;
-    T* acc = d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ;
-    #pragma unroll 1
+    const rsrc_t rin = mkbuf(task < 3 ? d.phip : d.psip, tabn);
+    const rsrc_t rout = mkbuf(task < 3 ? d.Kt : d.psiw, tabn);
+    const rsrc_t ra = mkbuf(d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
+    const unsigned fg = 2 * g * K::FSZ;
+#pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
       T zr[E], zi[E];
-      const T* in_j = inner + (size_t)j * K::FSZ;
+      const unsigned tj = j * K::FSZ;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const int o = k * K::NT + t;
-        const T a = in_j[o];
-        zr[k] = sg[o] * a;
-        zi[k] = sg[K::FSZ + o] * a;
+        const unsigned o = k * K::NT;
+        const T a = bld<T>(rin, vo, (tj + o) * S);
+        zr[k] = bld<T>(rs, vo, (fg + o) * S) * a;
+        zi[k] = bld<T>(rs, vo, (fg + K::FSZ + o) * S) * a;
       }
       eng.inv2(zr, zi);
 #pragma unroll
       for (int n = 0; n < E; ++n) {
-        const T f = f0[n * K::NT + t];
+        const T f = bld<T>(rw, vo, (4 * K::FSZ + n * K::NT) * S);
         zr[n] *= f;
         zi[n] *= f;
       }
       eng.fwd2(zr, zi);
-      const T* out_j = outer + (size_t)j * K::FSZ;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const int o = k * K::NT + t;
-        const T a = out_j[o];
-        if (j == 0) {
-          acc[o] = a * zr[k];
-          acc[K::FSZ + o] = a * zi[k];
-        } else {
-          acc[o] += a * zr[k];
-          acc[K::FSZ + o] += a * zi[k];
+        const unsigned o = k * K::NT;
+        const T a = bld<T>(rout, vo, (tj + o) * S);
+        T ar = a * zr[k], ai = a * zi[k];
+        if (j != 0) {
+          ar += bld<T>(ra, vo, o * S);
+          ai += bld<T>(ra, vo, (K::FSZ + o) * S);
         }
+        bst<T>(ra, ar, vo, o * S);
+        bst<T>(ra, ai, vo, (K::FSZ + o) * S);
       }
     }
     T zr[E], zi[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-      const int o = k * K::NT + t;
-      zr[k] = acc[o];
-      zi[k] = acc[K::FSZ + o];
+      const unsigned o = k * K::NT;
+      zr[k] = bld<T>(ra, vo, o * S);
+      zi[k] = bld<T>(ra, vo, (K::FSZ + o) * S);
     }
     eng.inv2(zr, zi);
 #pragma unroll
-    for (int n = 0; n < E; ++n) out[n * K::NT + t] = zr[n];
+    for (int n = 0; n < E; ++n) bst<T>(ro, zr[n], vo, (n * K::NT) * S);
   } else {
-    T S[E];
+    T Sacc[E];
 #pragma unroll
-    for (int n = 0; n < E; ++n) S[n] = 0;
+    for (int n = 0; n < E; ++n) Sacc[n] = 0;
     const T wj = (T)(kPi / d.J);
-    #pragma unroll 1
+    const rsrc_t rps = mkbuf(d.psi, tabn);
+    const rsrc_t rpp = mkbuf(d.psip, tabn);
+#pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
-      const T* ps = d.psi + (size_t)j * K::FSZ;
-      const T* pp = d.psip + (size_t)j * K::FSZ;
-      #pragma unroll 1
+      const unsigned tj = j * K::FSZ;
+#pragma unroll 1
       for (int mu = 0; mu < 4; ++mu) {
-        const T* s = spec + mu * 2 * K::FSZ;
+        const unsigned fm = 2 * mu * K::FSZ;
         T zr[E], zi[E];
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          const int o = k * K::NT + t;
-          const T ar = s[o], ai = s[K::FSZ + o], a = ps[o], b = pp[o];
+          const unsigned o = k * K::NT;
+          const T ar = bld<T>(rs, vo, (fm + o) * S), ai = bld<T>(rs, vo, (fm + K::FSZ + o) * S);
+          const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
           // w_hat psi + i w_hat psi'
           zr[k] = ar * a - ai * b;
           zi[k] = ai * a + ar * b;
@@ -289,11 +328,11 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
         eng.inv2(zr, zi);
         const T e = mu == 0 ? wj : -wj;
 #pragma unroll
-        for (int n = 0; n < E; ++n) S[n] += e * zr[n] * zi[n];
+        for (int n = 0; n < E; ++n) Sacc[n] += e * zr[n] * zi[n];
       }
     }
 #pragma unroll
-    for (int n = 0; n < E; ++n) out[n * K::NT + t] = S[n];
+    for (int n = 0; n < E; ++n) bst<T>(ro, Sacc[n], vo, (n * K::NT) * S);
   }
 }
 
@@ -303,169 +342,202 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
 // packed transforms), then for each nu and each pair of mu the packed
 // convolution Phi = IFFT(psi'_j FFT(w_mu s_nu)), and
 //   o_nu += (pi/J) w_m sum_mu eta_mu s_mu Phi_mu,nu.
+// When the four shifted fields fit in registers next to the working field
+// (SREG), they stay there for the whole (j, m) step; otherwise they go
+// through a per-workgroup buffer in global memory.
+#ifndef QB_I3_SREG_VGPRS
+#define QB_I3_SREG_VGPRS 100
+#endif
+template <typename T, int E>
+struct I3Regs {
+  static constexpr bool SREG = 6 * E * (int)sizeof(T) / 4 <= QB_I3_SREG_VGPRS;
+};
+
+template <typename T>
+__device__ __forceinline__ T pick4(int i, T a, T b, T c, T d) {
+  return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
+}
+
 template <typename T, int P, int E>
-__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3(DevPlan<T> d, int ncells) {
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_per_eu(Kern<T, P, E>::WAVES))) void k_i3(DevPlan<T> d, int ncells) {
   using K = Kern<T, P, E>;
+  constexpr unsigned S = sizeof(T);
+  constexpr bool SREG = I3Regs<T, E>::SREG;
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
-  setup(eng, smem, d.twc, d.tws);
+  setup(eng, smem, d.tw);
   const int task = xcd_task(blockIdx.x, gridDim.x);
   const int cell = task / d.J;
   const int j = task % d.J;
-  const int t = threadIdx.x;
-  const T* spec = d.spec + (size_t)cell * 4 * 2 * K::FSZ;
-  const T* wP = d.wP + (size_t)cell * 5 * K::FSZ;
-  T* sbuf = d.i3s + ((size_t)cell * d.J + j) * 4 * K::FSZ;
-  T* obuf = d.i3o + ((size_t)cell * d.J + j) * 4 * K::FSZ;
-  const T* mult = d.psips + (size_t)j * K::FSZ;
+  const unsigned vo = threadIdx.x * S;
+  const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
+  const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
+  const rsrc_t ro = mkbuf(d.i3o + ((size_t)cell * d.J + j) * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rb = mkbuf(SREG ? d.i3o : d.i3s + ((size_t)cell * d.J + j) * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
-  #pragma unroll 1
+  T s[SREG ? 4 : 1][SREG ? E : 1];
+#pragma unroll 1
   for (int m = 0; m < d.M; ++m) {
     const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
-    const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2;
+    const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
     const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
     // shifted fields
-    #pragma unroll 1
+#pragma unroll
     for (int pr = 0; pr < 2; ++pr) {
-      const T* sa = spec + (2 * pr) * 2 * K::FSZ;
-      const T* sb = spec + (2 * pr + 1) * 2 * K::FSZ;
+      const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
       T zr[E], zi[E];
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const int o = k * K::NT + t;
-        const int ky = eng.bk(k);
+        const unsigned o = k * K::NT;
         T er, ei;
-        cmul(pxr, pxi, py[2 * ky], py[2 * ky + 1], er, ei);
+        cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
         T ar, ai, br, bi;
-        cmul(sa[o], sa[K::FSZ + o], er, ei, ar, ai);
-        cmul(sb[o], sb[K::FSZ + o], er, ei, br, bi);
+        cmul(bld<T>(rs, vo, (fa + o) * S), bld<T>(rs, vo, (fa + K::FSZ + o) * S), er, ei, ar, ai);
+        cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
         zr[k] = ar - bi;
         zi[k] = ai + br;
       }
       eng.inv2(zr, zi);
 #pragma unroll
       for (int n = 0; n < E; ++n) {
-        sbuf[(2 * pr) * K::FSZ + n * K::NT + t] = zr[n];
-        sbuf[(2 * pr + 1) * K::FSZ + n * K::NT + t] = zi[n];
+        if constexpr (SREG) {
+          s[SREG ? 2 * pr : 0][n] = zr[n];
+          s[SREG ? 2 * pr + 1 : 0][n] = zi[n];
+        } else {
+          bst<T>(rb, zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
+          bst<T>(rb, zi[n], vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
+        }
       }
     }
     const T wgt = d.wm[m];
-    #pragma unroll 1
+#pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
-      T tmp[E];
-#pragma unroll
-      for (int n = 0; n < E; ++n) tmp[n] = 0;
-      #pragma unroll 1
+#pragma unroll 1
       for (int mp = 0; mp < 2; ++mp) {
         const int m0 = 2 * mp, m1 = 2 * mp + 1;
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
-          const int o = n * K::NT + t;
-          const T s = sbuf[nu * K::FSZ + o];
-          zr[n] = wP[m0 * K::FSZ + o] * s;
-          zi[n] = wP[m1 * K::FSZ + o] * s;
+          const unsigned o = n * K::NT;
+          T sv;
+          if constexpr (SREG)
+            sv = pick4(nu, s[0][n], s[SREG ? 1 : 0][n], s[SREG ? 2 : 0][n], s[SREG ? 3 : 0][n]);
+          else
+            sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
+          zr[n] = bld<T>(rw, vo, (m0 * K::FSZ + o) * S) * sv;
+          zi[n] = bld<T>(rw, vo, (m1 * K::FSZ + o) * S) * sv;
+          if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
         }
         eng.fwd2(zr, zi);
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          const T a = mult[k * K::NT + t];
+          const T a = bld<T>(rm, vo, (k * K::NT) * S);
           zr[k] *= a;
           zi[k] *= a;
+          if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
         eng.inv2(zr, zi);
-        const T e0 = m0 == 0 ? (T)1 : (T)-1;
+        const T e0 = m0 == 0 ? wgt : -wgt;
+        const bool first = m == 0 && mp == 0;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
-          const int o = n * K::NT + t;
-          tmp[n] += e0 * sbuf[m0 * K::FSZ + o] * zr[n] - sbuf[m1 * K::FSZ + o] * zi[n];
+          const unsigned o = n * K::NT;
+          T sa, sb;
+          if constexpr (SREG) {
+            sa = mp == 0 ? s[0][n] : s[SREG ? 2 : 0][n];
+            sb = mp == 0 ? s[SREG ? 1 : 0][n] : s[SREG ? 3 : 0][n];
+          } else {
+            sa = bld<T>(rb, vo, (m0 * K::FSZ + o) * S);
+            sb = bld<T>(rb, vo, (m1 * K::FSZ + o) * S);
+          }
+          const unsigned off = (nu * K::FSZ + o) * S;
+          T v = e0 * sa * zr[n] - wgt * sb * zi[n];
+          if (!first) v += bld<T>(ro, vo, off);
+          bst<T>(ro, v, vo, off);
+          if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
-      }
-#pragma unroll
-      for (int n = 0; n < E; ++n) {
-        const int o = nu * K::FSZ + n * K::NT + t;
-        if (m == 0)
-          obuf[o] = wgt * tmp[n];
-        else
-          obuf[o] += wgt * tmp[n];
       }
     }
   }
 }
 
+// Real-space P-grid fields of C, elementwise: sums the per-j partials of I_3
+// and assembles the Pauli components (C_c + pi (A + B + Cq), see k_combine)
+// into i3sum[cell][mu].
+template <typename T>
+__global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)ncells * fsz) return;
+  const size_t cell = idx / fsz, e = idx % fsz;
+  const size_t per = (size_t)4 * fsz;
+  const T* o3 = d.i3o + cell * d.J * per + e;
+  T b[4] = {0, 0, 0, 0};
+  for (int j = 0; j < d.J; ++j)
+    for (int nu = 0; nu < 4; ++nu) b[nu] += o3[(size_t)j * per + (size_t)nu * fsz];
+  const T* wp = d.wP + cell * 5 * fsz + e;
+  const T* tr = d.terms + cell * 8 * fsz + e;
+  const T w0 = wp[0], w1 = wp[fsz], w2 = wp[2 * fsz], w3 = wp[3 * fsz];
+  const T g1 = tr[0], g2 = tr[fsz], g3 = tr[2 * fsz];
+  const T y0 = tr[3 * fsz], y1 = tr[4 * fsz], y2 = tr[5 * fsz], y3 = tr[6 * fsz];
+  const T Sv = tr[7 * fsz];
+  const T pi = (T)kPi, two = (T)2;
+  T* r = d.i3sum + cell * per + e;
+  // A: 2 <w3, w4>_eta (1 - W1); B: -2 <w3, w4>_eta (eta w2).sigma;
+  // Cq: f0(v+u) {W1, (eta w2).sigma};  C_c,k = -2 eps_klm A^G_l w_m
+  r[0] = pi * (two * Sv * ((T)1 - w0) - two * b[0] + two * (y0 * w0 - y1 * w1 - y2 * w2 - y3 * w3));
+  r[fsz] = -two * (g2 * w3 - g3 * w2) + pi * (-two * Sv * w1 + two * b[1] + two * (y0 * w1 - y1 * w0));
+  r[2 * fsz] = -two * (g3 * w1 - g1 * w3) + pi * (-two * Sv * w2 + two * b[2] + two * (y0 * w2 - y2 * w0));
+  r[3 * fsz] = -two * (g1 * w2 - g2 * w1) + pi * (-two * Sv * w3 + two * b[3] + two * (y0 * w3 - y3 * w0));
+}
+
 // ------------------------------------------------------------------ combine
-// Assemble the real-space P-grid fields of C (Pauli components), transform,
-// keep Xi without its -N/2 rows and columns, and evaluate on the velocity
-// grid:  c[mu][cell][i][j].
+// Transform the assembled real-space P-grid fields of C (Pauli components,
+// k_assemble), keep Xi without its -N/2 rows and columns, and evaluate on
+// the velocity grid:  c[mu][cell][i][j].
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T* __restrict__ c, int cell0) {
   using K = Kern<T, P, E>;
+  constexpr unsigned S = sizeof(T);
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
-  setup(eng, smem, d.twc, d.tws);
+  setup(eng, smem, d.tw);
   const int lc = blockIdx.x;
   const int cell = cell0 + lc;
-  const int t = threadIdx.x;
   const int N = P / 2;
-  const T* wP = d.wP + (size_t)lc * 5 * K::FSZ;
-  const T* tr = d.terms + (size_t)lc * 8 * K::FSZ;
-  const T* o3 = d.i3o + (size_t)lc * d.J * 4 * K::FSZ;
-  const T pi = (T)kPi;
+  const unsigned vo = threadIdx.x * S;
+  const rsrc_t r3 = mkbuf(d.i3sum + (size_t)lc * 4 * K::FSZ, 4 * K::FSZ);
   const size_t cs = (size_t)d.Nx * N * N;
-  #pragma unroll 1
+#pragma unroll 1
   for (int pr = 0; pr < 2; ++pr) {
     T zr[E], zi[E];
 #pragma unroll
     for (int n = 0; n < E; ++n) {
-      const int o = n * K::NT + t;
-      const T w0 = wP[o], w1 = wP[K::FSZ + o], w2 = wP[2 * K::FSZ + o], w3 = wP[3 * K::FSZ + o];
-      const T g1 = tr[o], g2 = tr[K::FSZ + o], g3 = tr[2 * K::FSZ + o];
-      const T y0 = tr[3 * K::FSZ + o], y1 = tr[4 * K::FSZ + o], y2 = tr[5 * K::FSZ + o],
-              y3 = tr[6 * K::FSZ + o];
-      const T S = tr[7 * K::FSZ + o];
-      T b0 = 0, b1 = 0, b2 = 0, b3 = 0;
-      #pragma unroll 1
-      for (int j = 0; j < d.J; ++j) {
-        const T* oj = o3 + (size_t)j * 4 * K::FSZ + o;
-        b0 += oj[0];
-        b1 += oj[K::FSZ];
-        b2 += oj[2 * K::FSZ];
-        b3 += oj[3 * K::FSZ];
-      }
-      T r[4];
-      // C_c,k = -2 eps_klm A^G_l w_m
-      const T cc1 = -(T)2 * (g2 * w3 - g3 * w2);
-      const T cc2 = -(T)2 * (g3 * w1 - g1 * w3);
-      const T cc3 = -(T)2 * (g1 * w2 - g2 * w1);
-      r[0] = pi * ((T)2 * S * ((T)1 - w0) - (T)2 * b0 + (T)2 * (y0 * w0 - y1 * w1 - y2 * w2 - y3 * w3));
-      r[1] = cc1 + pi * (-(T)2 * S * w1 + (T)2 * b1 + (T)2 * (y0 * w1 - y1 * w0));
-      r[2] = cc2 + pi * (-(T)2 * S * w2 + (T)2 * b2 + (T)2 * (y0 * w2 - y2 * w0));
-      r[3] = cc3 + pi * (-(T)2 * S * w3 + (T)2 * b3 + (T)2 * (y0 * w3 - y3 * w0));
-      zr[n] = r[2 * pr];
-      zi[n] = r[2 * pr + 1];
+      const unsigned o = n * K::NT;
+      zr[n] = bld<T>(r3, vo, ((2 * pr) * K::FSZ + o) * S);
+      zi[n] = bld<T>(r3, vo, ((2 * pr + 1) * K::FSZ + o) * S);
     }
     eng.fwd2(zr, zi);
     const int bx = centered<P>(eng.line);
     const bool kx_in = bx > -N / 2 && bx < N / 2;
-    const T s = (T)1 / (T)(P * P);
+    const T sc = (T)1 / (T)(P * P);
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const int by = centered<P>(eng.bk(k));
       const bool in = kx_in && by > -N / 2 && by < N / 2;
-      zr[k] = in ? zr[k] * s : (T)0;
-      zi[k] = in ? zi[k] * s : (T)0;
+      zr[k] = in ? zr[k] * sc : (T)0;
+      zi[k] = in ? zi[k] * sc : (T)0;
     }
     eng.inv2(zr, zi);
     const int y = eng.line;
+    if (((eng.q | y) & 1) == 0) {
+      T* ca = c + (2 * pr) * cs + (size_t)cell * N * N + (centered<P>(y) / 2 + N / 2);
+      T* cb = ca + cs;
 #pragma unroll
-    for (int n = 0; n < E; ++n) {
-      const int x = eng.sx(n);
-      if (((x | y) & 1) == 0) {
-        const int i = centered<P>(x) / 2 + N / 2;
-        const int jj = centered<P>(y) / 2 + N / 2;
-        const size_t idx = ((size_t)cell * N + i) * N + jj;
-        c[(2 * pr) * cs + idx] = zr[n];
-        c[(2 * pr + 1) * cs + idx] = zi[n];
+      for (int n = 0; n < E; ++n) {
+        const int i = vel_index<P, K::TPR>(eng.q, n);
+        ca[i * N] = zr[n];
+        cb[i * N] = zi[n];
       }
     }
   }

@@ -87,8 +87,8 @@ struct qb_plan_s {
   int P, E, NT, TPR;
   size_t bytes = 0;
   std::vector<void*> allocs;
-  void *twc, *tws, *phip, *Kt, *psi, *psip, *psiw, *psips, *phx, *phy, *wm;
-  void *spec, *wP, *terms, *acc, *i3s, *i3o;
+  void *tw, *phip, *Kt, *psi, *psip, *psiw, *psips, *phx, *phy, *wm;
+  void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum;
   void *st0, *st1, *st2, *cbuf, *bcw;
   double* flux;
   qb::BcDev bl, br;
@@ -164,11 +164,14 @@ bool build_tables(qb_plan_s* pl) {
   const int P = pl->P, E = pl->E, NT = pl->NT, TPR = pl->TPR, J = p.J, M = p.M;
   const double L = p.L, R = p.R;
   const size_t FSZ = (size_t)P * P;
-  std::vector<double> twc(P), tws(P);
-  for (int i = 0; i < P; ++i) {
-    twc[i] = std::cos(2.0 * M_PI * i / P);
-    tws[i] = std::sin(2.0 * M_PI * i / P);
-  }
+  // (cos, sin)(2 pi q k / P) at [q][k], q < TPR, k < E  (engine twiddles)
+  std::vector<double> tw(2 * P);
+  for (int q = 0; q < TPR; ++q)
+    for (int k = 0; k < E; ++k) {
+      const int i = q * E + k;
+      tw[2 * i] = std::cos(2.0 * M_PI * ((q * k) % P) / P);
+      tw[2 * i + 1] = std::sin(2.0 * M_PI * ((q * k) % P) / P);
+    }
   std::vector<double> th_c(J), th_s(J), thp_c(J), thp_s(J);
   for (int j = 0; j < J; ++j) {
     th_c[j] = std::cos(j * M_PI / J);
@@ -222,7 +225,7 @@ bool build_tables(qb_plan_s* pl) {
         phy[o + 1] = std::sin(ay);
       }
     }
-  return upload<T>(pl, &pl->twc, twc) && upload<T>(pl, &pl->tws, tws) && upload<T>(pl, &pl->phip, phip) &&
+  return upload<T>(pl, &pl->tw, tw) && upload<T>(pl, &pl->phip, phip) &&
          upload<T>(pl, &pl->Kt, Kt) && upload<T>(pl, &pl->psi, psi) && upload<T>(pl, &pl->psip, psip) &&
          upload<T>(pl, &pl->psiw, psiw) && upload<T>(pl, &pl->psips, psips) && upload<T>(pl, &pl->phx, phx) &&
          upload<T>(pl, &pl->phy, phy) && upload<T>(pl, &pl->wm, wm);
@@ -294,14 +297,25 @@ bool build_bc(qb_plan_s* pl) {
          hip_ok(hipMemset(pl->flux, 0, 2 * sizeof(double)), "hipMemset");
 }
 
+// whether k_i3 keeps the shifted fields in registers for this (precision, P)
+template <typename T>
+bool i3_sreg(int P) {
+  switch (P) {
+    case 32: return qb::I3Regs<T, qb::Cfg<T, 32>::E>::SREG;
+    case 64: return qb::I3Regs<T, qb::Cfg<T, 64>::E>::SREG;
+    default: return qb::I3Regs<T, qb::Cfg<T, 128>::E>::SREG;
+  }
+}
+
 template <typename T>
 bool build_buffers(qb_plan_s* pl) {
   const qb_problem& p = pl->prob;
   const size_t FSZ = (size_t)pl->P * pl->P, C = p.Nx, J = p.J;
   const size_t st = (size_t)4 * C * p.N * p.N * sizeof(T);
+  if (!i3_sreg<T>(pl->P) && !pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T))) return false;
   return pl->alloc(&pl->spec, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->wP, C * 5 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->terms, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->acc, C * 14 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3sum, C * 4 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->st0, st) && pl->alloc(&pl->st1, st) && pl->alloc(&pl->st2, st) &&
          pl->alloc(&pl->cbuf, st);
 }
@@ -315,8 +329,7 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.M = pl->prob.M;
   d.P = pl->P;
   d.L = (T)pl->prob.L;
-  d.twc = (const T*)pl->twc;
-  d.tws = (const T*)pl->tws;
+  d.tw = (const T*)pl->tw;
   d.phip = (const T*)pl->phip;
   d.Kt = (const T*)pl->Kt;
   d.psi = (const T*)pl->psi;
@@ -332,8 +345,11 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.acc = (T*)pl->acc;
   d.i3s = (T*)pl->i3s;
   d.i3o = (T*)pl->i3o;
+  d.i3sum = (T*)pl->i3sum;
   return d;
 }
+
+int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 // C[w] for cells [0, ncells) of the Pauli state w -> c (both [4][Nx][N][N])
 template <typename T, int P>
@@ -350,6 +366,8 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t
   id = pl->begin(QB_K_I3, s);
   hipLaunchKernelGGL((qb::k_i3<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
+  const size_t nel = (size_t)ncells * P * P;
+  hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
   id = pl->begin(QB_K_COMBINE, s);
   hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, 0);
   pl->end(id, s);
@@ -365,8 +383,6 @@ bool collision_any(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
   }
   return false;
 }
-
-int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 template <typename T>
 bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
