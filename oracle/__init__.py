@@ -32,6 +32,10 @@ What it computes, and where the paper defines it:
 * ``step``       -- the time-splitting step of Sec. 4 (half transport,
                     collision + magnetic field, half transport) and the
                     fluid moments (eq. density, velocity, internal_energy).
+* ``adjoint``    -- reverse-mode derivatives of the above (the transpose of
+                    each forward step, run backwards): C'(w)^T lam, the
+                    transport and splitting steps, and the gradient of a
+                    final-time observable in the initial state and B(x).
 
 Readings of passages where the paper is silent or garbled are marked
 "Reading:" where they are applied.
