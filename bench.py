@@ -70,6 +70,55 @@ def run_gpu(wl, precision, steps, warmup):
     return t1 - t0, kern, tot0, tot1
 
 
+def run_adjoint(steps, every):
+    """Adjoint/forward time ratio on the configuration-5 workload (Nx = 128,
+    N = 32, J = 32, M = 32, complex128, periodic, B = (0, 0, 0.5), dt = 1e-3):
+    `steps` plain forward steps (qb_step) against the backward pass of the
+    checkpointed autograd integration (recompute each segment with
+    qb_step_trace, then qb_adjoint_step per step), for the gradient of
+    dx h^2 sum g(x_j) tr(sigma_z W(T)) in W0 and B."""
+    import torch
+    import paper_1408_1782_amd as qb
+    import workloads
+
+    wl = workloads.config(5)
+    plan = qb.Plan(qb.Problem(wl.Nx, wl.N, wl.J, wl.M, wl.L, wl.R, "f64"))
+    plan.enable_adjoint()
+    W0 = torch.from_numpy(wl.W0).cuda().contiguous()
+    B = torch.from_numpy(wl.B).cuda().contiguous()
+    h2 = (2 * wl.L / wl.N) ** 2
+    g = torch.from_numpy(workloads.adjoint_loss_weight(wl.Nx)).cuda()
+
+    def loss_of(WT):
+        return h2 / wl.Nx * (g[:, None, None] * (WT[..., 0, 0] - WT[..., 1, 1]).real).sum()
+
+    # warm-up: one forward and one reverse step
+    Wr = W0.clone().requires_grad_(True)
+    loss_of(qb.evolve(plan, Wr, B, wl.dt, 1, every)).backward()
+    torch.cuda.synchronize()
+    W = W0.clone()
+    t0 = time.perf_counter()
+    plan.step(W, B, wl.dt, steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"[adjoint] forward {steps} steps {t_fwd:.3f} s")
+    Wr = W0.clone().requires_grad_(True)
+    Br = B.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    loss = loss_of(qb.evolve(plan, Wr, Br, wl.dt, steps, every))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    log(f"[adjoint] checkpointed forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+    plan.close()
+    return {"workload": "adjoint_fd_periodic_B", "Nx": wl.Nx, "N": wl.N, "J": wl.J, "M": wl.M, "dtype": "f64",
+            "steps": steps, "checkpoint_every": every, "forward_s": t_fwd, "forward_with_checkpoints_s": t1 - t0,
+            "backward_s": t2 - t1, "ratio": (t2 - t1) / t_fwd,
+            "grad_norms": {"W0": float(Wr.grad.abs().max()), "B": float(Br.grad.abs().max())}}
+
+
 def cpu_baseline(wl):
     """The CPU oracle on a bounded sample of the same workload: one collision
     evaluation of one cell plus one transport half-step over all cells."""
@@ -119,6 +168,9 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nx", type=int, default=None, help="fewer cells (profiling runs)")
+    ap.add_argument("--adj-steps", type=int, default=40,
+                    help="steps of the adjoint/forward measurement (0 skips it)")
+    ap.add_argument("--adj-every", type=int, default=20, help="checkpoint interval of the adjoint run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -167,6 +219,10 @@ def main():
         out["roofline_f64"] = roof(k64, "f64")
         out["moment_drift_f64"] = drift(a64, b64)
     out["adjoint_forward_ratio"] = None
+    if args.adj_steps > 0:
+        adj = run_adjoint(args.adj_steps, args.adj_every)
+        out["adjoint_forward_ratio"] = adj["ratio"]
+        out["adjoint"] = adj
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

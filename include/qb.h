@@ -136,6 +136,54 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 /* float64 moments [Nx][7] of W ([Nx][N][N][2][2] complex). */
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Reverse mode (adjoint).  Gradients of a real scalar l follow torch's
+ * convention for complex arrays: the cotangent G of a state W satisfies
+ * dl = Re sum conj(G) dW, i.e. G = dl/dRe W + i dl/dIm W.  Since every map
+ * here reads only the Hermitian part of W, the returned G is Hermitian,
+ * G = (1/2) sum_mu g_mu sigma_mu with g_mu = dl/dw_mu (Sec. 3.1).  The
+ * limiter of eq. minmod is differentiated on the branch it takes at the
+ * forward state.
+ * ------------------------------------------------------------------------- */
+
+/* Allocate the plan's adjoint workspace (synchronous, idempotent).  Every
+ * call below returns QB_EWORKSPACE until this has succeeded. */
+qb_status qb_plan_enable_adjoint(qb_plan plan);
+
+/* G = C'(W)^T lam for `ncells` cells: the transpose of the linearization of
+ * qb_collision at W applied to the cotangent lam of C (Sec. 3.2; C is a
+ * polynomial of degree three in the Pauli components of W).
+ * W, lam, G: [ncells][N][N][2][2] complex; G distinct from W and lam. */
+qb_status qb_collision_vjp(qb_plan plan, const void* W, const void* lam, void* G, int32_t ncells,
+                           void* stream);
+
+/* G = T'(W)^T lam for one qb_transport_step of length dt taken at W
+ * (eq. slopeLimiterStep, Sec. 2 walls).  W, lam, G: [Nx][N][N][2][2] complex. */
+qb_status qb_transport_vjp(qb_plan plan, const void* W, double dt, const void* lam, void* G, void* stream);
+
+/* Bytes of one step record written by qb_step_trace. */
+size_t qb_trace_bytes(qb_plan plan);
+
+/* As qb_step (no moments), and for each step n writes a record of
+ * qb_trace_bytes(plan) bytes at trace + n * qb_trace_bytes(plan): the step's
+ * input state, the Heun stage and the Heun output (internal layout; only
+ * qb_adjoint_step reads it).  trace: device buffer of nsteps records. */
+qb_status qb_step_trace(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, void* trace,
+                        void* stream);
+
+/* Reverse of one qb_step of length dt (Sec. 4 splitting with the Heun
+ * stages):  lam = (dS/dW)^T lam_next and gB += (dS/dB)^T lam_next, S the
+ * step taken from the state W with field B.
+ *   W        : step input [Nx][N][N][2][2] complex; read only when record is NULL.
+ *   record   : NULL (the step's forward stages are recomputed: two collision
+ *              evaluations) or this step's record from qb_step_trace.
+ *   B        : float64 [Nx][3] or NULL (no field).
+ *   lam_next : cotangent of the step output; lam: cotangent of its input
+ *              (may alias lam_next).
+ *   gB       : float64 [Nx][3], accumulated (+=), or NULL. */
+qb_status qb_adjoint_step(qb_plan plan, const void* W, const void* record, const double* B, double dt,
+                          const void* lam_next, void* lam, double* gB, void* stream);
+
 /* Kernel timing.  With profiling on, every kernel the plan launches is
  * bracketed by a pair of HIP events on its stream; qb_profile_read
  * synchronizes those events and returns, for one kernel class, the summed
@@ -149,7 +197,9 @@ typedef enum {
   QB_K_TRANSPORT = 4,
   QB_K_HEUN = 5,
   QB_K_MOMENTS = 6,
-  QB_K_COUNT = 7
+  QB_K_I3_ADJOINT = 7, /* transpose of the I_3 kernel */
+  QB_K_ADJOINT = 8,    /* the other reverse-mode kernels */
+  QB_K_COUNT = 9
 } qb_kernel;
 qb_status qb_profile(qb_plan plan, int32_t enable);
 qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_t* launches);

@@ -15,4 +15,12 @@ from ._lib import (  # noqa: F401
     lib_path,
 )
 
-__all__ = ["BC", "Plan", "Problem", "QBError", "load", "lib_path"]
+
+def evolve(plan, W0, B, dt, nsteps, checkpoint_every=20):
+    """Differentiable splitting-step integration (see ``autograd.evolve``)."""
+    from .autograd import evolve as _evolve
+
+    return _evolve(plan, W0, B, dt, nsteps, checkpoint_every)
+
+
+__all__ = ["BC", "Plan", "Problem", "QBError", "evolve", "load", "lib_path"]

@@ -15,7 +15,8 @@ QB_OK, QB_EINVAL, QB_ENOTSUP, QB_ECFL, QB_EWORKSPACE, QB_EHIP = 0, -1, -2, -3, -
 QB_F64, QB_F32 = 0, 1
 QB_PERIODIC, QB_DIRICHLET, QB_MAXWELL = 0, 1, 2
 _KINDS = {"periodic": QB_PERIODIC, "dirichlet": QB_DIRICHLET, "maxwell": QB_MAXWELL}
-KERNELS = {"dft_in": 0, "terms": 1, "i3": 2, "combine": 3, "transport": 4, "heun": 5, "moments": 6}
+KERNELS = {"dft_in": 0, "terms": 1, "i3": 2, "combine": 3, "transport": 4, "heun": 5, "moments": 6,
+           "i3_adjoint": 7, "adjoint": 8}
 
 # names the header declares (checked by the CPU tests)
 EXPORTS = (
@@ -26,6 +27,12 @@ EXPORTS = (
     "qb_transport_step",
     "qb_step",
     "qb_moments",
+    "qb_plan_enable_adjoint",
+    "qb_collision_vjp",
+    "qb_transport_vjp",
+    "qb_trace_bytes",
+    "qb_step_trace",
+    "qb_adjoint_step",
     "qb_profile",
     "qb_profile_read",
     "qb_strerror",
@@ -94,6 +101,18 @@ def _declare(lib):
     lib.qb_step.restype = i32
     lib.qb_moments.argtypes = [vp, vp, vp, vp]
     lib.qb_moments.restype = i32
+    lib.qb_plan_enable_adjoint.argtypes = [vp]
+    lib.qb_plan_enable_adjoint.restype = i32
+    lib.qb_collision_vjp.argtypes = [vp, vp, vp, vp, i32, vp]
+    lib.qb_collision_vjp.restype = i32
+    lib.qb_transport_vjp.argtypes = [vp, vp, dbl, vp, vp, vp]
+    lib.qb_transport_vjp.restype = i32
+    lib.qb_trace_bytes.argtypes = [vp]
+    lib.qb_trace_bytes.restype = ctypes.c_size_t
+    lib.qb_step_trace.argtypes = [vp, vp, vp, dbl, i32, vp, vp]
+    lib.qb_step_trace.restype = i32
+    lib.qb_adjoint_step.argtypes = [vp, vp, vp, vp, dbl, vp, vp, vp, vp]
+    lib.qb_adjoint_step.restype = i32
     lib.qb_profile.argtypes = [vp, i32]
     lib.qb_profile.restype = i32
     lib.qb_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
@@ -254,6 +273,90 @@ class Plan:
             mp = _ptr(moments)
         _check(self.lib.qb_step(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _stream()), "qb_step")
         return W
+
+    def _field(self, B):
+        import torch
+
+        p = self.problem
+        if B is None:
+            return ctypes.c_void_p(0)
+        if B.dtype != torch.float64 or not B.is_cuda or tuple(B.shape) != (p.Nx, 3) or not B.is_contiguous():
+            raise ValueError("B must be a contiguous CUDA float64 tensor [Nx, 3]")
+        return _ptr(B)
+
+    # ------------------------------------------------------------ reverse mode
+    def enable_adjoint(self):
+        """qb_plan_enable_adjoint: allocate the adjoint workspace (once)."""
+        _check(self.lib.qb_plan_enable_adjoint(self.handle), "qb_plan_enable_adjoint")
+
+    def collision_vjp(self, W, lam, G=None, ncells=None):
+        """qb_collision_vjp: G = C'(W)^T lam (torch's complex-gradient convention)."""
+        import torch
+
+        n = W.shape[0] if ncells is None else int(ncells)
+        self._check_state(W, n)
+        self._check_state(lam, n)
+        if G is None:
+            G = torch.empty_like(W)
+        self._check_state(G, n)
+        _check(self.lib.qb_collision_vjp(self.handle, _ptr(W), _ptr(lam), _ptr(G), n, _stream()),
+               "qb_collision_vjp")
+        return G
+
+    def transport_vjp(self, W, dt, lam, G=None):
+        """qb_transport_vjp: G = T'(W)^T lam for one transport step of length dt."""
+        import torch
+
+        self._check_state(W)
+        self._check_state(lam)
+        if G is None:
+            G = torch.empty_like(W)
+        self._check_state(G)
+        _check(self.lib.qb_transport_vjp(self.handle, _ptr(W), float(dt), _ptr(lam), _ptr(G), _stream()),
+               "qb_transport_vjp")
+        return G
+
+    @property
+    def trace_bytes(self):
+        """qb_trace_bytes: bytes of one step record of qb_step_trace."""
+        return self.lib.qb_trace_bytes(self.handle)
+
+    def new_trace(self, nsteps):
+        import torch
+
+        return torch.empty(int(nsteps) * self.trace_bytes, dtype=torch.uint8, device="cuda")
+
+    def step_trace(self, W, B, dt, nsteps, trace):
+        """qb_step_trace: nsteps steps in place, one record per step in `trace`."""
+        self._check_state(W)
+        if trace.numel() < nsteps * self.trace_bytes or not trace.is_cuda:
+            raise ValueError("trace too small")
+        _check(self.lib.qb_step_trace(self.handle, _ptr(W), self._field(B), float(dt), int(nsteps), _ptr(trace),
+                                      _stream()), "qb_step_trace")
+        return W
+
+    def adjoint_step(self, lam_next, B, dt, W=None, record=None, lam=None, gB=None):
+        """qb_adjoint_step: cotangent of a step's input from that of its output;
+        `record` (a view of a step_trace buffer) or the input state W."""
+        import torch
+
+        self._check_state(lam_next)
+        if lam is None:
+            lam = torch.empty_like(lam_next)
+        self._check_state(lam)
+        wp = ctypes.c_void_p(0)
+        if W is not None:
+            self._check_state(W)
+            wp = _ptr(W)
+        rp = ctypes.c_void_p(0) if record is None else _ptr(record)
+        gp = ctypes.c_void_p(0)
+        if gB is not None:
+            if gB.dtype != torch.float64 or tuple(gB.shape) != (self.problem.Nx, 3) or not gB.is_contiguous():
+                raise ValueError("gB must be a contiguous CUDA float64 tensor [Nx, 3]")
+            gp = _ptr(gB)
+        _check(self.lib.qb_adjoint_step(self.handle, wp, rp, self._field(B), float(dt), _ptr(lam_next), _ptr(lam),
+                                        gp, _stream()), "qb_adjoint_step")
+        return lam
 
     def moments(self, W, out=None):
         """qb_moments: float64 [Nx, 7] moments of W."""

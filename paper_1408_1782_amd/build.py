@@ -17,7 +17,7 @@ FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-shared",
-    # packed FP32 instructions off (correctness of some of their forms on the test machines)
+    # no packed FP32 instructions (v_pk_*_f32): every FP32 op is issued unpacked
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     f"-I{os.path.join(ROOT, 'include')}",

@@ -55,6 +55,16 @@ struct DevPlan {
   T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
   T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
   T* i3sum;  // [cells][4][P*P]     I_3 summed over j
+  // adjoint work buffers (present once the plan's adjoint is enabled)
+  T* lamP;   // [cells][4][P*P]     cotangent of the assembled fields, row real
+  T* acot;   // [cells][16][P*P]    assembly cotangents: g (3), y (4), S (1), b (4), w direct (4)
+  T* gspec;  // [cells][11][2][P*P] cotangents of w_hat from I_1 (3), I_4 (4), I_2 (4), col spec
+  T* gf0;    // [cells][7][P*P]     f0 cotangents of the I_1 / I_4 tasks, row real
+  T* tsb;    // [cells][8][2][P*P]  scratch of the I_1 / I_4 / I_2 adjoint tasks
+  T* i3g;    // [cells][J][8][P*P]  I_3 adjoint per (cell, j): w cotangent (4, row real),
+             //                     packed w_hat cotangents (2 pairs x re/im, col spec)
+  T* i3sb;   // [cells][J][4][P*P]  cotangent of the shifted fields of the current (j, m)
+  T* gsum;   // [cells][8][P*P]     gathered cotangents (k_grad_pre)
 };
 
 // ------------------------------------------------------------------ helpers
@@ -610,6 +620,37 @@ __global__ void k_maxwell_flux(const T* __restrict__ w, double* __restrict__ flu
   if (threadIdx.x == 0) flux[wall] = h * h * red[0];
 }
 
+// Value of the ghost-extended state at cell c (c < 0 or c >= Nx are ghost
+// cells), component mu, velocity point e = i*N + j (Sec. 2 walls):
+// periodic wrap; at a wall, the inflow state at incoming v_x (Dirichlet Phi,
+// Maxwell (1 - alpha) W_b(-v_x, v_y) + alpha W_FD Fbar / Z), a copy of the
+// adjacent cell otherwise; the row v_x = -L has no mirror and counts as
+// outgoing at a Maxwell wall.
+template <typename T>
+__device__ __forceinline__ T ext_value(const T* __restrict__ w, const T* __restrict__ bcw,
+                                       const double* __restrict__ flux, const BcDev& bl, const BcDev& br, int mu,
+                                       int c, int e, int i, T vx, int Nx, int N) {
+  const int per = N * N;
+  const size_t cs = (size_t)Nx * per;
+  if (c >= 0 && c < Nx) return w[mu * cs + (size_t)c * per + e];
+  if (bl.kind == 0) {
+    c = ((c % Nx) + Nx) % Nx;
+    return w[mu * cs + (size_t)c * per + e];
+  }
+  const bool left = c < 0;
+  const BcDev& bc = left ? bl : br;
+  const int adj = left ? 0 : Nx - 1;
+  const T* ws = bcw + (size_t)(left ? 0 : 1) * 4 * per + (size_t)mu * per;
+  bool inflow = left ? (vx > (T)0) : (vx < (T)0);
+  if (bc.kind == 2 && !left && i == 0) inflow = false;  // v_x = -L: no mirror
+  if (!inflow) return w[mu * cs + (size_t)adj * per + e];
+  if (bc.kind == 1) return ws[e];
+  const int mi = N - i;  // mirrored v_x row
+  const T wb = w[mu * cs + (size_t)adj * per + (size_t)mi * N + (e % N)];
+  const double fz = flux[left ? 0 : 1] / bc.Z;
+  return (T)(1.0 - bc.alpha) * wb + (T)(bc.alpha * fz) * ws[e];
+}
+
 // One step of eq. slopeLimiterStep of length dt, all cells and velocities.
 // bcw: [2 walls][4][N][N] wall states (Dirichlet Phi or Maxwell W_FD).
 template <typename T>
@@ -625,39 +666,9 @@ __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T
   const T vx = h * (T)(i - N / 2);
   const T dx = (T)1 / (T)Nx;
   const size_t cs = (size_t)Nx * per;
-  const bool periodic = bl.kind == 0;
-  // inflow factors per wall
   T gval[4][5];
-  for (int mu = 0; mu < 4; ++mu) {
-    for (int o = -2; o <= 2; ++o) {
-      int c = cell + o;
-      T v;
-      if (c >= 0 && c < Nx) {
-        v = w[mu * cs + (size_t)c * per + e];
-      } else if (periodic) {
-        c = ((c % Nx) + Nx) % Nx;
-        v = w[mu * cs + (size_t)c * per + e];
-      } else {
-        const bool left = c < 0;
-        const BcDev& bc = left ? bl : br;
-        const int adj = left ? 0 : Nx - 1;
-        const T* ws = bcw + (size_t)(left ? 0 : 1) * 4 * per + (size_t)mu * per;
-        bool inflow = left ? (vx > (T)0) : (vx < (T)0);
-        if (bc.kind == 2 && !left && i == 0) inflow = false;  // v_x = -L: no mirror
-        if (!inflow) {
-          v = w[mu * cs + (size_t)adj * per + e];
-        } else if (bc.kind == 1) {
-          v = ws[e];
-        } else {
-          const int mi = N - i;  // mirrored v_x row
-          const T wb = w[mu * cs + (size_t)adj * per + (size_t)mi * N + (e % N)];
-          const double fz = flux[left ? 0 : 1] / bc.Z;
-          v = (T)(1.0 - bc.alpha) * wb + (T)(bc.alpha * fz) * ws[e];
-        }
-      }
-      gval[mu][o + 2] = v;
-    }
-  }
+  for (int mu = 0; mu < 4; ++mu)
+    for (int o = -2; o <= 2; ++o) gval[mu][o + 2] = ext_value(w, bcw, flux, bl, br, mu, cell + o, e, i, vx, Nx, N);
   const T nu = dt * vx / dx;
   const T sg = vx > (T)0 ? (T)1 : (vx < (T)0 ? (T)-1 : (T)0);
   const T lim = (T)0.5 * (sg - nu);

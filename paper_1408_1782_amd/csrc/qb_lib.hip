@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "qb.h"
+#include "qb_adjoint.hpp"
 #include "qb_kernels.hpp"
 
 using qb::DevPlan;
@@ -91,6 +92,13 @@ struct qb_plan_s {
   void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum;
   void *st0, *st1, *st2, *cbuf, *bcw;
   double* flux;
+  // adjoint workspace (qb_plan_enable_adjoint)
+  bool adjoint = false;
+  void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
+       *i3sb = nullptr, *gsum = nullptr;
+  void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
+       *cg = nullptr, *g0 = nullptr, *ext = nullptr;
+  double* lflux = nullptr;
   qb::BcDev bl, br;
   // kernel timing
   bool profiling = false;
@@ -321,6 +329,23 @@ bool build_buffers(qb_plan_s* pl) {
 }
 
 template <typename T>
+bool build_adjoint(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  const size_t FSZ = (size_t)pl->P * pl->P, C = p.Nx, J = p.J, b = sizeof(T);
+  const size_t st = (size_t)4 * C * p.N * p.N * b;
+  if (!pl->i3s && !pl->alloc(&pl->i3s, C * J * 4 * FSZ * b)) return false;
+  void** states[] = {&pl->wn, &pl->wa, &pl->w1, &pl->wb, &pl->lb, &pl->ls, &pl->la, &pl->cg, &pl->g0};
+  for (void** q : states)
+    if (!pl->alloc(q, st)) return false;
+  return pl->alloc(&pl->lamP, C * 4 * FSZ * b) && pl->alloc(&pl->acot, C * 16 * FSZ * b) &&
+         pl->alloc(&pl->gspec, C * 22 * FSZ * b) && pl->alloc(&pl->gf0, C * 7 * FSZ * b) &&
+         pl->alloc(&pl->tsb, C * 16 * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
+         pl->alloc(&pl->i3sb, C * J * 4 * FSZ * b) && pl->alloc(&pl->gsum, C * 8 * FSZ * b) &&
+         pl->alloc(&pl->ext, (size_t)4 * (C + 4) * p.N * p.N * b) &&
+         pl->alloc((void**)&pl->lflux, 2 * sizeof(double));
+}
+
+template <typename T>
 DevPlan<T> devplan(qb_plan_s* pl) {
   DevPlan<T> d;
   d.Nx = pl->prob.Nx;
@@ -346,6 +371,14 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.i3s = (T*)pl->i3s;
   d.i3o = (T*)pl->i3o;
   d.i3sum = (T*)pl->i3sum;
+  d.lamP = (T*)pl->lamP;
+  d.acot = (T*)pl->acot;
+  d.gspec = (T*)pl->gspec;
+  d.gf0 = (T*)pl->gf0;
+  d.tsb = (T*)pl->tsb;
+  d.i3g = (T*)pl->i3g;
+  d.i3sb = (T*)pl->i3sb;
+  d.gsum = (T*)pl->gsum;
   return d;
 }
 
@@ -398,6 +431,72 @@ bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
   return hip_ok(hipGetLastError(), "transport launch");
 }
 
+// dst = T(dt) src (src unchanged)
+template <typename T>
+bool transport_to(qb_plan_s* pl, const T* src, T* dst, double dt, hipStream_t s) {
+  T* a = (T*)src;
+  T* b = dst;
+  return transport<T>(pl, a, b, dt, s);
+}
+
+// ------------------------------------------------------------------ adjoint pipelines
+// out = C'(w)^T lam for cells [0, ncells) (Pauli state layout, gradients)
+template <typename T, int P>
+bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, hipStream_t s) {
+  constexpr int E = qb::Cfg<T, P>::E;
+  constexpr int NT = qb::Fft2<T, P, E>::NT;
+  DevPlan<T> d = devplan<T>(pl);
+  int id = pl->begin(QB_K_DFT_IN, s);
+  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, 0);
+  pl->end(id, s);
+  id = pl->begin(QB_K_TERMS, s);
+  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  pl->end(id, s);
+  id = pl->begin(QB_K_ADJOINT, s);
+  hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, 0);
+  const size_t nel = (size_t)ncells * P * P;
+  hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
+  hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  pl->end(id, s);
+  id = pl->begin(QB_K_I3_ADJOINT, s);
+  hipLaunchKernelGGL((qb::k_i3_vjp<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+  pl->end(id, s);
+  id = pl->begin(QB_K_ADJOINT, s);
+  hipLaunchKernelGGL((qb::k_grad_pre<T>), dim3(blocks(nel * 8, 256)), dim3(256), 0, s, d, ncells, P * P);
+  hipLaunchKernelGGL((qb::k_grad_out<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, out, 0);
+  pl->end(id, s);
+  return hip_ok(hipGetLastError(), "collision adjoint launch");
+}
+
+template <typename T>
+bool collision_vjp_any(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, hipStream_t s) {
+  switch (pl->P) {
+    case 32: return collision_vjp_pipeline<T, 32>(pl, w, lam, out, ncells, s);
+    case 64: return collision_vjp_pipeline<T, 64>(pl, w, lam, out, ncells, s);
+    case 128: return collision_vjp_pipeline<T, 128>(pl, w, lam, out, ncells, s);
+  }
+  return false;
+}
+
+// out = T'(x)^T lam for one transport step of length dt taken at state x
+template <typename T>
+bool transport_vjp(qb_plan_s* pl, const T* x, const T* lam, T* out, double dt, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const int lm = p.left.kind == QB_MAXWELL, rm = p.right.kind == QB_MAXWELL;
+  const size_t n = (size_t)p.Nx * p.N * p.N, ne = (size_t)(p.Nx + 4) * p.N * p.N;
+  const int id = pl->begin(QB_K_ADJOINT, s);
+  if (lm || rm) hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, x, pl->flux, p.Nx, p.N, p.L, lm, rm);
+  hipLaunchKernelGGL((qb::k_transport_vjp_ext<T>), dim3(blocks(ne, 256)), dim3(256), 0, s, x, lam, (T*)pl->ext,
+                     (const T*)pl->bcw, pl->flux, pl->bl, pl->br, (T)dt, p.Nx, p.N, (T)p.L);
+  if (lm || rm)
+    hipLaunchKernelGGL((qb::k_maxwell_lflux<T>), dim3(2), dim3(256), 0, s, (const T*)pl->ext, (const T*)pl->bcw,
+                       pl->lflux, pl->bl, pl->br, p.Nx, p.N);
+  hipLaunchKernelGGL((qb::k_transport_vjp_fold<T>), dim3(blocks(n, 256)), dim3(256), 0, s, (const T*)pl->ext, out,
+                     pl->lflux, pl->bl, pl->br, p.Nx, p.N, (T)p.L);
+  pl->end(id, s);
+  return hip_ok(hipGetLastError(), "transport adjoint launch");
+}
+
 template <typename T>
 bool moments(qb_plan_s* pl, const T* w, double* mom, hipStream_t s) {
   const qb_problem& p = pl->prob;
@@ -425,6 +524,22 @@ bool from_state(qb_plan_s* pl, const T* w, void* W, int ncells, hipStream_t s) {
 }
 
 template <typename T>
+bool to_cot(qb_plan_s* pl, const void* G, T* g, int ncells, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)ncells * p.N * p.N;
+  hipLaunchKernelGGL((qb::k_api_to_cot<T, T>), dim3(blocks(n, 256)), dim3(256), 0, s, (const T*)G, g, ncells, p.N,
+                     p.Nx);
+  return hip_ok(hipGetLastError(), "layout launch");
+}
+template <typename T>
+bool from_cot(qb_plan_s* pl, const T* g, void* G, int ncells, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)ncells * p.N * p.N;
+  hipLaunchKernelGGL((qb::k_cot_to_api<T, T>), dim3(blocks(n, 256)), dim3(256), 0, s, g, (T*)G, ncells, p.N, p.Nx);
+  return hip_ok(hipGetLastError(), "layout launch");
+}
+
+template <typename T>
 qb_status do_collision(qb_plan_s* pl, const void* W, void* C, int ncells, hipStream_t s) {
   T* w = (T*)pl->st0;
   T* c = (T*)pl->cbuf;
@@ -435,7 +550,8 @@ qb_status do_collision(qb_plan_s* pl, const void* W, void* C, int ncells, hipStr
 }
 
 template <typename T>
-qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps, double* mom, hipStream_t s) {
+qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps, double* mom, T* trace,
+                  hipStream_t s) {
   const qb_problem& p = pl->prob;
   T* cur = (T*)pl->st0;
   T* tmp = (T*)pl->st2;
@@ -445,17 +561,25 @@ qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps
   const size_t mstride = (size_t)p.Nx * 7;
   if (!to_state<T, T>(pl, W, cur, p.Nx, s)) return QB_EHIP;
   if (mom && !moments<T>(pl, cur, mom, s)) return QB_EHIP;
+  const size_t sb = 4 * n * sizeof(T);
   for (int it = 0; it < nsteps; ++it) {
+    // trace record of this step: [step input, Heun stage 1, Heun output]
+    T* rec = trace ? trace + (size_t)it * 3 * 4 * n : nullptr;
+    if (rec && !hip_ok(hipMemcpyAsync(rec, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy")) return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     if (!collision_any<T>(pl, cur, c, p.Nx, s)) return QB_EHIP;
     int id = pl->begin(QB_K_HEUN, s);
     hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 1);
     pl->end(id, s);
+    if (rec && !hip_ok(hipMemcpyAsync(rec + 4 * n, w1, sb, hipMemcpyDeviceToDevice, s), "trace copy"))
+      return QB_EHIP;
     if (!collision_any<T>(pl, w1, c, p.Nx, s)) return QB_EHIP;
     id = pl->begin(QB_K_HEUN, s);
     hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 2);
     pl->end(id, s);
     if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
+    if (rec && !hip_ok(hipMemcpyAsync(rec + 8 * n, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy"))
+      return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     if (mom && !moments<T>(pl, cur, mom + (it + 1) * mstride, s)) return QB_EHIP;
   }
@@ -483,6 +607,83 @@ qb_status do_moments(qb_plan_s* pl, const void* W, double* mom, hipStream_t s) {
   if (!to_state<T, T>(pl, W, cur, pl->prob.Nx, s)) return QB_EHIP;
   if (!moments<T>(pl, cur, mom, s)) return QB_EHIP;
   return QB_OK;
+}
+
+template <typename T>
+qb_status do_collision_vjp(qb_plan_s* pl, const void* W, const void* lam, void* G, int ncells, hipStream_t s) {
+  T* w = (T*)pl->wn;
+  T* g = (T*)pl->g0;
+  T* out = (T*)pl->cg;
+  if (!to_state<T, T>(pl, W, w, ncells, s) || !to_cot<T>(pl, lam, g, ncells, s)) return QB_EHIP;
+  if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
+  return from_cot<T>(pl, out, G, ncells, s) ? QB_OK : QB_EHIP;
+}
+
+template <typename T>
+qb_status do_transport_vjp(qb_plan_s* pl, const void* W, double dt, const void* lam, void* G, hipStream_t s) {
+  const int Nx = pl->prob.Nx;
+  T* w = (T*)pl->wn;
+  T* g = (T*)pl->g0;
+  T* out = (T*)pl->lb;
+  if (!to_state<T, T>(pl, W, w, Nx, s) || !to_cot<T>(pl, lam, g, Nx, s)) return QB_EHIP;
+  if (!transport_vjp<T>(pl, w, g, out, dt, s)) return QB_EHIP;
+  return from_cot<T>(pl, out, G, Nx, s) ? QB_OK : QB_EHIP;
+}
+
+// Reverse of one splitting step S = T(dt/2) . Heun(dt) . T(dt/2):
+//   lam_b = T'(wb)^T lam_next
+//   lam_1 = lam_b / 2 + dt/2 F'(w1)^T lam_b
+//   lam_a = lam_b / 2 + lam_1 + dt F'(wa)^T lam_1
+//   lam   = T'(wn)^T lam_a
+// with wn the step input, wa = T(dt/2) wn, w1 the Heun stage and wb the Heun
+// output (taken from the trace record, or recomputed here).
+template <typename T>
+qb_status do_adjoint_step(qb_plan_s* pl, const void* W, const void* record, const double* B, double dt,
+                          const void* lam_next, void* lam, double* gB, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const size_t n = (size_t)p.Nx * p.N * p.N;
+  const size_t sb = 4 * n * sizeof(T);
+  T *wn, *w1, *wb;
+  T* wa = (T*)pl->wa;
+  T* c = (T*)pl->cbuf;
+  if (record) {
+    wn = (T*)record;
+    w1 = wn + 4 * n;
+    wb = wn + 8 * n;
+    if (!transport_to<T>(pl, wn, wa, 0.5 * dt, s)) return QB_EHIP;
+  } else {
+    wn = (T*)pl->wn;
+    w1 = (T*)pl->w1;
+    wb = (T*)pl->wb;
+    if (!to_state<T, T>(pl, W, wn, p.Nx, s)) return QB_EHIP;
+    if (!transport_to<T>(pl, wn, wa, 0.5 * dt, s)) return QB_EHIP;
+    if (!collision_any<T>(pl, wa, c, p.Nx, s)) return QB_EHIP;
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, wa, w1, c, B, (T)dt, p.Nx, p.N, 1);
+    if (!hip_ok(hipMemcpyAsync(wb, wa, sb, hipMemcpyDeviceToDevice, s), "copy")) return QB_EHIP;
+    if (!collision_any<T>(pl, w1, c, p.Nx, s)) return QB_EHIP;
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, wb, w1, c, B, (T)dt, p.Nx, p.N, 2);
+    if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
+  }
+  T* g0 = (T*)pl->g0;
+  T* lb = (T*)pl->lb;
+  T* l1 = (T*)pl->ls;
+  T* la = (T*)pl->la;
+  T* cg = (T*)pl->cg;
+  if (!to_cot<T>(pl, lam_next, g0, p.Nx, s)) return QB_EHIP;
+  if (!transport_vjp<T>(pl, wb, g0, lb, 0.5 * dt, s)) return QB_EHIP;
+  if (!collision_vjp_any<T>(pl, w1, lb, cg, p.Nx, s)) return QB_EHIP;
+  int id = pl->begin(QB_K_ADJOINT, s);
+  hipLaunchKernelGGL((qb::k_heun_vjp<T>), dim3(p.Nx), dim3(256), 0, s, lb, (const T*)nullptr, cg, w1, B, l1, gB,
+                     (T)dt, p.Nx, p.N, 2);
+  pl->end(id, s);
+  if (!collision_vjp_any<T>(pl, wa, l1, cg, p.Nx, s)) return QB_EHIP;
+  id = pl->begin(QB_K_ADJOINT, s);
+  hipLaunchKernelGGL((qb::k_heun_vjp<T>), dim3(p.Nx), dim3(256), 0, s, lb, l1, cg, wa, B, la, gB, (T)dt, p.Nx, p.N,
+                     1);
+  pl->end(id, s);
+  if (!hip_ok(hipGetLastError(), "heun adjoint launch")) return QB_EHIP;
+  if (!transport_vjp<T>(pl, wn, la, g0, 0.5 * dt, s)) return QB_EHIP;
+  return from_cot<T>(pl, g0, lam, p.Nx, s) ? QB_OK : QB_EHIP;
 }
 
 qb_status validate_bc(const qb_bc& b) {
@@ -576,8 +777,63 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
   qb_status st = check_cfl(plan, 0.5 * dt);
   if (st != QB_OK) return st;
   hipStream_t s = (hipStream_t)stream;
-  if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, moments_out, s);
-  return do_step<float>(plan, W, B, dt, nsteps, moments_out, s);
+  if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, moments_out, nullptr, s);
+  return do_step<float>(plan, W, B, dt, nsteps, moments_out, nullptr, s);
+}
+
+qb_status qb_plan_enable_adjoint(qb_plan plan) {
+  if (!plan) return QB_EINVAL;
+  if (plan->adjoint) return QB_OK;
+  const bool ok = plan->prob.precision == QB_F64 ? build_adjoint<double>(plan) : build_adjoint<float>(plan);
+  if (!ok) return QB_EHIP;
+  plan->adjoint = true;
+  return QB_OK;
+}
+
+size_t qb_trace_bytes(qb_plan plan) {
+  if (!plan) return 0;
+  const qb_problem& p = plan->prob;
+  const size_t b = p.precision == QB_F64 ? sizeof(double) : sizeof(float);
+  return (size_t)3 * 4 * p.Nx * p.N * p.N * b;
+}
+
+qb_status qb_step_trace(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, void* trace,
+                        void* stream) {
+  if (!plan || !W || !trace || nsteps < 0) return QB_EINVAL;
+  qb_status st = check_cfl(plan, 0.5 * dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, nullptr, (double*)trace, s);
+  return do_step<float>(plan, W, B, dt, nsteps, nullptr, (float*)trace, s);
+}
+
+qb_status qb_collision_vjp(qb_plan plan, const void* W, const void* lam, void* G, int32_t ncells, void* stream) {
+  if (!plan || !W || !lam || !G || ncells < 1) return QB_EINVAL;
+  if (ncells > plan->prob.Nx || !plan->adjoint) return QB_EWORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_collision_vjp<double>(plan, W, lam, G, ncells, s);
+  return do_collision_vjp<float>(plan, W, lam, G, ncells, s);
+}
+
+qb_status qb_transport_vjp(qb_plan plan, const void* W, double dt, const void* lam, void* G, void* stream) {
+  if (!plan || !W || !lam || !G) return QB_EINVAL;
+  if (!plan->adjoint) return QB_EWORKSPACE;
+  qb_status st = check_cfl(plan, dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_transport_vjp<double>(plan, W, dt, lam, G, s);
+  return do_transport_vjp<float>(plan, W, dt, lam, G, s);
+}
+
+qb_status qb_adjoint_step(qb_plan plan, const void* W, const void* record, const double* B, double dt,
+                          const void* lam_next, void* lam, double* gB, void* stream) {
+  if (!plan || (!W && !record) || !lam_next || !lam) return QB_EINVAL;
+  if (!plan->adjoint) return QB_EWORKSPACE;
+  qb_status st = check_cfl(plan, 0.5 * dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_adjoint_step<double>(plan, W, record, B, dt, lam_next, lam, gB, s);
+  return do_adjoint_step<float>(plan, W, record, B, dt, lam_next, lam, gB, s);
 }
 
 qb_status qb_moments(qb_plan plan, const void* W, double* mom, void* stream) {
@@ -631,6 +887,6 @@ qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_
   return QB_OK;
 }
 
-int32_t qb_version(void) { return 100; }
+int32_t qb_version(void) { return 200; }
 
 }  // extern "C"

@@ -12,6 +12,11 @@ Each output is an .npz next to this script:
                       M = 32, B = (0, 0, 0.5), dt = 1e-3): 2 steps.
   c3_cells.npz        configuration 3 (N = 64, J = 32, M = 64): C[W] of the
                       initial state at 3 sampled cells.
+  c5_reduced_grad.npz configuration 5 recipe on a reduced instance (Nx = 8,
+                      N = 16, J = M = 8, 20 steps, dt = 1e-3, B = (0, 0, 0.5),
+                      periodic): the final state, the observable
+                      dx h^2 sum g(x_j) tr(sigma_z W(T)) and its gradients in
+                      the initial Pauli state and in B.
 """
 import os
 import sys
@@ -24,6 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import workloads as wl  # noqa: E402
+from oracle import adjoint as oad  # noqa: E402
 from oracle import collision as oc  # noqa: E402
 from oracle import pauli  # noqa: E402
 from oracle import step as ostep  # noqa: E402
@@ -80,8 +86,26 @@ def make_c3():
     np.savez_compressed(os.path.join(HERE, "c3_cells.npz"), cells=np.array(C3_CELLS), c=np.stack(out))
 
 
+C5_REDUCED = dict(Nx=8, N=16, J=8, M=8, steps=20)
+
+
+def make_c5():
+    r = C5_REDUCED
+    w = wl.config(5, Nx=r["Nx"], N=r["N"])
+    t = oc.Tables(w.N, w.L, w.R, r["J"], r["M"])
+    per = {"kind": "periodic"}
+    g = wl.adjoint_loss_weight(w.Nx)
+    lam = oad.observable_weights(g, w.N, w.L)
+    t0 = time.time()
+    wT, gw, gB = oad.trajectory_gradient(pauli.to_pauli(w.W0), w.B, w.dt, r["steps"], lam, w.L, w.R,
+                                         r["J"], r["M"], per, per, t)
+    print(f"  {time.time() - t0:.1f} s", flush=True)
+    np.savez_compressed(os.path.join(HERE, "c5_reduced_grad.npz"), final=wT, loss=np.sum(lam * wT),
+                        grad_w0=gw, grad_B=gB, weight=g)
+
+
 if __name__ == "__main__":
-    todo = sys.argv[1:] or ["c1", "c2", "c3"]
+    todo = sys.argv[1:] or ["c1", "c2", "c3", "c5"]
     for name in todo:
         print(name, flush=True)
-        {"c1": make_c1, "c2": make_c2, "c3": make_c3}[name]()
+        {"c1": make_c1, "c2": make_c2, "c3": make_c3, "c5": make_c5}[name]()

@@ -71,3 +71,9 @@ def test_null_arguments_rejected():
     assert lib.qb_collision(None, None, None, 1, None) == _lib.QB_EINVAL
     assert lib.qb_step(None, None, None, 1e-3, 1, None, None) == _lib.QB_EINVAL
     assert lib.qb_plan_create(None, None) == _lib.QB_EINVAL
+    assert lib.qb_plan_enable_adjoint(None) == _lib.QB_EINVAL
+    assert lib.qb_collision_vjp(None, None, None, None, 1, None) == _lib.QB_EINVAL
+    assert lib.qb_transport_vjp(None, None, 1e-3, None, None, None) == _lib.QB_EINVAL
+    assert lib.qb_step_trace(None, None, None, 1e-3, 1, None, None) == _lib.QB_EINVAL
+    assert lib.qb_adjoint_step(None, None, None, None, 1e-3, None, None, None, None) == _lib.QB_EINVAL
+    assert lib.qb_trace_bytes(None) == 0
