@@ -137,6 +137,58 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * FFT tile shapes.  Every padded-grid transform runs in one workgroup that
+ * holds the P x P field in registers, E elements per thread and P / E
+ * threads per line.  Compiled shapes: P = 32: E = 16 (default), 8;
+ * P = 64: E = 32 (default), 16; P = 128: E = 32.
+ * ------------------------------------------------------------------------- */
+
+/* Use tile shape E on this plan (QB_ENOTSUP if not compiled for its P).
+ * Synchronous the first time a shape is used (builds its tables). */
+qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
+
+/* Autotuner: time the collision pipeline on the plan's first `ncells` cells
+ * for every compiled tile shape and keep the fastest (synchronous; it
+ * overwrites the plan's internal state buffer).  The choice is cached per
+ * (precision, N, J, M, ncells) for the life of the process.  *tile (may be
+ * NULL) receives the chosen E. */
+qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent problems (uneven Nx and N) advanced together:
+ * problems with the same N share one concatenated cell array, so each
+ * collision kernel is one launch over all their cells; transport runs per
+ * problem with its own walls.
+ * ------------------------------------------------------------------------- */
+typedef struct qb_batch_s* qb_batch;
+
+/* Create a batch of nprob problems (each valid for qb_plan_create; all with
+ * the same precision, J, L and R; problems with equal N must have equal M).
+ * Allocates all device memory (synchronous). */
+qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, qb_batch* out);
+qb_status qb_batch_destroy(qb_batch batch);
+size_t qb_batch_bytes(qb_batch batch);
+
+/* Run the autotuner (qb_plan_tune) for every N group of the batch. */
+qb_status qb_batch_tune(qb_batch batch, void* stream);
+
+#define QB_BATCH_GRAPH 1 /* record the whole call as a HIP graph and replay it */
+
+/* nsteps splitting steps (as qb_step) of every problem, in place.
+ *   W       : host array of nprob device pointers, W[m] [Nx_m][N_m][N_m][2][2] complex.
+ *   B       : host array of nprob device pointers (float64 [Nx_m][3], or NULL
+ *             entries for no field), or NULL.
+ *   moments : host array of nprob device pointers (float64
+ *             [nsteps + 1][Nx_m][7], or NULL entries), or NULL.
+ *   flags   : QB_BATCH_GRAPH records the launch sequence of the call in a HIP
+ *             graph on first use and replays it while W, B, moments, dt and
+ *             nsteps are unchanged (no HIP graph memset nodes are used).
+ * QB_ECFL if (dt/2) L Nx_m > 1 for any problem.  The first call that asks
+ * for moments with more snapshots than before allocates scratch for them. */
+qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, double dt, int32_t nsteps,
+                        double* const* moments, int32_t flags, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Reverse mode (adjoint).  Gradients of a real scalar l follow torch's
  * convention for complex arrays: the cotangent G of a state W satisfies
  * dl = Re sum conj(G) dW, i.e. G = dl/dRe W + i dl/dIm W.  Since every map

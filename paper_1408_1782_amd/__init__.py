@@ -8,6 +8,7 @@ calling into the library does, and fails loudly when ``libqb.so`` is missing.
 """
 from ._lib import (  # noqa: F401
     BC,
+    Batch,
     Plan,
     Problem,
     QBError,
@@ -23,4 +24,4 @@ def evolve(plan, W0, B, dt, nsteps, checkpoint_every=20):
     return _evolve(plan, W0, B, dt, nsteps, checkpoint_every)
 
 
-__all__ = ["BC", "Plan", "Problem", "QBError", "evolve", "load", "lib_path"]
+__all__ = ["BC", "Batch", "Plan", "Problem", "QBError", "evolve", "load", "lib_path"]

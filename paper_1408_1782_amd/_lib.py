@@ -33,6 +33,13 @@ EXPORTS = (
     "qb_trace_bytes",
     "qb_step_trace",
     "qb_adjoint_step",
+    "qb_plan_set_tile",
+    "qb_plan_tune",
+    "qb_batch_create",
+    "qb_batch_destroy",
+    "qb_batch_bytes",
+    "qb_batch_tune",
+    "qb_batch_step",
     "qb_profile",
     "qb_profile_read",
     "qb_strerror",
@@ -113,6 +120,20 @@ def _declare(lib):
     lib.qb_step_trace.restype = i32
     lib.qb_adjoint_step.argtypes = [vp, vp, vp, vp, dbl, vp, vp, vp, vp]
     lib.qb_adjoint_step.restype = i32
+    lib.qb_plan_set_tile.argtypes = [vp, i32]
+    lib.qb_plan_set_tile.restype = i32
+    lib.qb_plan_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
+    lib.qb_plan_tune.restype = i32
+    lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
+    lib.qb_batch_create.restype = i32
+    lib.qb_batch_destroy.argtypes = [vp]
+    lib.qb_batch_destroy.restype = i32
+    lib.qb_batch_bytes.argtypes = [vp]
+    lib.qb_batch_bytes.restype = ctypes.c_size_t
+    lib.qb_batch_tune.argtypes = [vp, vp]
+    lib.qb_batch_tune.restype = i32
+    lib.qb_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(vp), i32, vp]
+    lib.qb_batch_step.restype = i32
     lib.qb_profile.argtypes = [vp, i32]
     lib.qb_profile.restype = i32
     lib.qb_profile_read.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64)]
@@ -368,6 +389,20 @@ class Plan:
         _check(self.lib.qb_moments(self.handle, _ptr(W), _ptr(out), _stream()), "qb_moments")
         return out
 
+    # ------------------------------------------------------------ tiles
+    TILES = {32: (16, 8), 64: (32, 16), 128: (32,)}
+
+    def set_tile(self, E):
+        """qb_plan_set_tile: FFT tile shape (elements per thread) of this plan."""
+        _check(self.lib.qb_plan_set_tile(self.handle, int(E)), "qb_plan_set_tile")
+
+    def tune(self, ncells=None):
+        """qb_plan_tune: time every compiled tile shape, keep the fastest; returns E."""
+        e = ctypes.c_int32()
+        n = self.problem.Nx if ncells is None else int(ncells)
+        _check(self.lib.qb_plan_tune(self.handle, n, ctypes.byref(e), _stream()), "qb_plan_tune")
+        return e.value
+
     def profile(self, enable=True):
         """qb_profile: bracket every launch of this plan with HIP events."""
         _check(self.lib.qb_profile(self.handle, 1 if enable else 0), "qb_profile")
@@ -383,6 +418,7 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.qb_plan_destroy(self.handle)
+            self.handle = ctypes.c_void_p()
             self.handle = None
 
     def __del__(self):
@@ -407,3 +443,65 @@ def qb_step(plan, W, B=None, dt=1e-3, nsteps=1, moments=None):
 
 def qb_moments(plan, W, out=None):
     return plan.moments(W, out)
+
+
+QB_BATCH_GRAPH = 1
+
+
+class Batch:
+    """A qb_batch: independent problems (uneven Nx, N) advanced together."""
+
+    def __init__(self, problems):
+        import torch
+
+        self.lib = load()
+        self.problems = list(problems)
+        arr = (_Problem * len(self.problems))(*[p._c() for p in self.problems])
+        h = ctypes.c_void_p()
+        _check(self.lib.qb_batch_create(arr, len(self.problems), ctypes.byref(h)), "qb_batch_create")
+        self.handle = h
+        prec = {p.precision for p in self.problems}
+        self.cdtype = torch.complex128 if prec == {"f64"} else torch.complex64
+
+    @property
+    def nbytes(self):
+        return self.lib.qb_batch_bytes(self.handle)
+
+    def tune(self):
+        _check(self.lib.qb_batch_tune(self.handle, _stream()), "qb_batch_tune")
+
+    def step(self, Ws, Bs=None, dt=1e-3, nsteps=1, moments=None, graph=False):
+        """qb_batch_step: nsteps steps of every problem in place."""
+        import torch
+
+        n = len(self.problems)
+        if len(Ws) != n:
+            raise ValueError("one state per problem")
+        for W, p in zip(Ws, self.problems):
+            if not W.is_cuda or not W.is_contiguous() or W.dtype != self.cdtype:
+                raise ValueError(f"expected contiguous CUDA {self.cdtype} tensors")
+            if tuple(W.shape) != (p.Nx, p.N, p.N, 2, 2):
+                raise ValueError(f"expected shape [{p.Nx}, {p.N}, {p.N}, 2, 2], got {tuple(W.shape)}")
+        vp = ctypes.c_void_p
+        Wp = (vp * n)(*[W.data_ptr() for W in Ws])
+        Bp = None
+        if Bs is not None:
+            for B, p in zip(Bs, self.problems):
+                if B is not None and (B.dtype != torch.float64 or tuple(B.shape) != (p.Nx, 3)
+                                      or not B.is_contiguous()):
+                    raise ValueError("B entries must be contiguous CUDA float64 [Nx, 3] tensors or None")
+            Bp = (vp * n)(*[0 if B is None else B.data_ptr() for B in Bs])
+        Mp = None
+        if moments is not None:
+            for m, p in zip(moments, self.problems):
+                if m is not None and (m.dtype != torch.float64 or tuple(m.shape) != (nsteps + 1, p.Nx, 7)):
+                    raise ValueError("moments entries must be CUDA float64 [nsteps + 1, Nx, 7] or None")
+            Mp = (vp * n)(*[0 if m is None else m.data_ptr() for m in moments])
+        _check(self.lib.qb_batch_step(self.handle, Wp, Bp, float(dt), int(nsteps), Mp,
+                                      QB_BATCH_GRAPH if graph else 0, _stream()), "qb_batch_step")
+        return Ws
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.qb_batch_destroy(self.handle)
+            self.handle = ctypes.c_void_p()

@@ -613,7 +613,7 @@ __global__ void k_transport_vjp_ext(const T* __restrict__ w, const T* __restrict
     T we[5], la[5];
     for (int o = 0; o < 5; ++o) {
       const int kk = k - 2 + o;
-      we[o] = (kk >= 0 && kk < NE) ? ext_value(w, bcw, flux, bl, br, mu, kk - 2, e, i, vx, Nx, N) : (T)0;
+      we[o] = (kk >= 0 && kk < NE) ? ext_value(w, bcw, flux, bl, br, mu, kk - 2, e, i, vx, Nx, N, cs) : (T)0;
       const int oc = k - 4 + o;
       la[o] = (oc >= 0 && oc < Nx) ? lam[mu * cs + (size_t)oc * per + e] : (T)0;
     }

@@ -629,9 +629,8 @@ __global__ void k_maxwell_flux(const T* __restrict__ w, double* __restrict__ flu
 template <typename T>
 __device__ __forceinline__ T ext_value(const T* __restrict__ w, const T* __restrict__ bcw,
                                        const double* __restrict__ flux, const BcDev& bl, const BcDev& br, int mu,
-                                       int c, int e, int i, T vx, int Nx, int N) {
+                                       int c, int e, int i, T vx, int Nx, int N, size_t cs) {
   const int per = N * N;
-  const size_t cs = (size_t)Nx * per;
   if (c >= 0 && c < Nx) return w[mu * cs + (size_t)c * per + e];
   if (bl.kind == 0) {
     c = ((c % Nx) + Nx) % Nx;
@@ -653,9 +652,12 @@ __device__ __forceinline__ T ext_value(const T* __restrict__ w, const T* __restr
 
 // One step of eq. slopeLimiterStep of length dt, all cells and velocities.
 // bcw: [2 walls][4][N][N] wall states (Dirichlet Phi or Maxwell W_FD).
+// The Nx cells start at w / wn; components are Ntot * N * N apart (Ntot
+// the cell count of the whole array, which may hold several problems).
 template <typename T>
 __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T* __restrict__ bcw,
-                            const double* __restrict__ flux, BcDev bl, BcDev br, T dt, int Nx, int N, T L) {
+                            const double* __restrict__ flux, BcDev bl, BcDev br, T dt, int Nx, int N, T L,
+                            int Ntot) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = N * N;
   if (idx >= Nx * per) return;
@@ -665,10 +667,11 @@ __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T
   const T h = (T)2 * L / (T)N;
   const T vx = h * (T)(i - N / 2);
   const T dx = (T)1 / (T)Nx;
-  const size_t cs = (size_t)Nx * per;
+  const size_t cs = (size_t)Ntot * per;
   T gval[4][5];
   for (int mu = 0; mu < 4; ++mu)
-    for (int o = -2; o <= 2; ++o) gval[mu][o + 2] = ext_value(w, bcw, flux, bl, br, mu, cell + o, e, i, vx, Nx, N);
+    for (int o = -2; o <= 2; ++o)
+      gval[mu][o + 2] = ext_value(w, bcw, flux, bl, br, mu, cell + o, e, i, vx, Nx, N, cs);
   const T nu = dt * vx / dx;
   const T sg = vx > (T)0 ? (T)1 : (vx < (T)0 ? (T)-1 : (T)0);
   const T lim = (T)0.5 * (sg - nu);
@@ -682,6 +685,23 @@ __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T
                   lim * (-vx * (Sp - Sm) + av * (Sp - (T)2 * S0 + Sm));
     wn[mu * cs + idx] = g[2] + dt / ((T)2 * dx) * upd;
   }
+}
+
+// ------------------------------------------------------------------ batch helpers
+// dst[0..n) = src[0..n), or zeros for a NULL source (a problem without field)
+__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src ? src[i] : 0.0;
+}
+
+// one problem's moments [snap][Nx][7] out of the batch moments [snap][Ntot][7]
+__global__ void k_scatter_moments(const double* __restrict__ src, double* __restrict__ dst, int nsnap, int Ntot,
+                                  int off, int Nx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = Nx * 7;
+  if (i >= nsnap * per) return;
+  const int snap = i / per, r = i % per;
+  dst[i] = src[((size_t)snap * Ntot + off) * 7 + r];
 }
 
 // ------------------------------------------------------------------ moments

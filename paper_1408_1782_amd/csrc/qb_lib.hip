@@ -4,7 +4,10 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -86,9 +89,19 @@ int cfg_E(int precision, int P) {
 struct qb_plan_s {
   qb_problem prob;
   int P, E, NT, TPR;
+  int wcells;  // cells per collision launch (the workspace holds this many)
   size_t bytes = 0;
   std::vector<void*> allocs;
-  void *tw, *phip, *Kt, *psi, *psip, *psiw, *psips, *phx, *phy, *wm;
+  // quadrature tables in the FFT engine's element order, one set per tile
+  // shape E (elements per thread) that has been selected on this plan
+  struct TabSet {
+    int E = 0;
+    void *tw = nullptr, *phip = nullptr, *Kt = nullptr, *psi = nullptr, *psip = nullptr, *psiw = nullptr,
+         *psips = nullptr;
+  };
+  std::vector<TabSet> tabs;
+  int cur_tab = 0;
+  void *phx, *phy, *wm;  // natural order, independent of the tile
   void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum;
   void *st0, *st1, *st2, *cbuf, *bcw;
   double* flux;
@@ -167,11 +180,12 @@ inline size_t colspec_index(int kx, int ky, int E, int TPR, int NT) {
 inline int centered_h(int k, int P) { return k < P / 2 ? k : k - P; }
 
 template <typename T>
-bool build_tables(qb_plan_s* pl) {
+bool build_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
   const qb_problem& p = pl->prob;
-  const int P = pl->P, E = pl->E, NT = pl->NT, TPR = pl->TPR, J = p.J, M = p.M;
+  const int P = pl->P, TPR = P / E, NT = P * TPR, J = p.J;
   const double L = p.L, R = p.R;
   const size_t FSZ = (size_t)P * P;
+  ts.E = E;
   // (cos, sin)(2 pi q k / P) at [q][k], q < TPR, k < E  (engine twiddles)
   std::vector<double> tw(2 * P);
   for (int q = 0; q < TPR; ++q)
@@ -216,6 +230,42 @@ bool build_tables(qb_plan_s* pl) {
       }
     }
   }
+  return upload<T>(pl, &ts.tw, tw) && upload<T>(pl, &ts.phip, phip) && upload<T>(pl, &ts.Kt, Kt) &&
+         upload<T>(pl, &ts.psi, psi) && upload<T>(pl, &ts.psip, psip) && upload<T>(pl, &ts.psiw, psiw) &&
+         upload<T>(pl, &ts.psips, psips);
+}
+
+// Make tile shape E current: build its table set on first use.
+template <typename T>
+bool select_tile(qb_plan_s* pl, int E) {
+  int idx = -1;
+  for (size_t i = 0; i < pl->tabs.size(); ++i)
+    if (pl->tabs[i].E == E) idx = (int)i;
+  if (idx < 0) {
+    qb_plan_s::TabSet ts;
+    if (!build_layout_tables<T>(pl, E, ts)) return false;
+    pl->tabs.push_back(ts);
+    idx = (int)pl->tabs.size() - 1;
+  }
+  pl->cur_tab = idx;
+  pl->E = E;
+  pl->TPR = pl->P / E;
+  pl->NT = pl->P * pl->TPR;
+  return true;
+}
+
+// Gauss-Legendre weights and the separable modulation phases of
+// eq. approxH-JM (natural frequency order, independent of the tile).
+template <typename T>
+bool build_phases(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  const int P = pl->P, J = p.J, M = p.M;
+  const double L = p.L, R = p.R;
+  std::vector<double> th_c(J), th_s(J);
+  for (int j = 0; j < J; ++j) {
+    th_c[j] = std::cos(j * M_PI / J);
+    th_s[j] = std::sin(j * M_PI / J);
+  }
   std::vector<double> gx, gw;
   gauss_legendre(M, gx, gw);
   std::vector<double> phx((size_t)J * M * P * 2), phy((size_t)J * M * P * 2), wm(M);
@@ -233,10 +283,12 @@ bool build_tables(qb_plan_s* pl) {
         phy[o + 1] = std::sin(ay);
       }
     }
-  return upload<T>(pl, &pl->tw, tw) && upload<T>(pl, &pl->phip, phip) &&
-         upload<T>(pl, &pl->Kt, Kt) && upload<T>(pl, &pl->psi, psi) && upload<T>(pl, &pl->psip, psip) &&
-         upload<T>(pl, &pl->psiw, psiw) && upload<T>(pl, &pl->psips, psips) && upload<T>(pl, &pl->phx, phx) &&
-         upload<T>(pl, &pl->phy, phy) && upload<T>(pl, &pl->wm, wm);
+  return upload<T>(pl, &pl->phx, phx) && upload<T>(pl, &pl->phy, phy) && upload<T>(pl, &pl->wm, wm);
+}
+
+template <typename T>
+bool build_tables(qb_plan_s* pl) {
+  return build_phases<T>(pl) && select_tile<T>(pl, pl->E);
 }
 
 // Pauli components of W_FD (eq. W_FermiDirac) on the velocity grid: [4][N][N]
@@ -271,14 +323,15 @@ void fd_pauli(const qb_fd& s, int N, double L, double* out) {
     }
 }
 
+// Wall tables of problem p (Dirichlet Phi or Maxwell W_FD on the velocity
+// grid, the Maxwell normalization Z) in device memory owned by `owner`.
 template <typename T>
-bool build_bc(qb_plan_s* pl) {
-  const qb_problem& p = pl->prob;
+bool build_bc_for(qb_plan_s* owner, const qb_problem& p, qb::BcDev& bl, qb::BcDev& br, void** bcw, double** flux) {
   const int N = p.N;
   const size_t per = (size_t)N * N;
   std::vector<double> bw(2 * 4 * per, 0.0);
   const qb_bc* bcs[2] = {&p.left, &p.right};
-  qb::BcDev* dv[2] = {&pl->bl, &pl->br};
+  qb::BcDev* dv[2] = {&bl, &br};
   const double h = 2.0 * p.L / N;
   for (int wall = 0; wall < 2; ++wall) {
     const qb_bc& b = *bcs[wall];
@@ -300,27 +353,21 @@ bool build_bc(qb_plan_s* pl) {
       dv[wall]->Z = h * h * Z;
     }
   }
-  if (!upload<T>(pl, &pl->bcw, bw)) return false;
-  return pl->alloc((void**)&pl->flux, 2 * sizeof(double)) &&
-         hip_ok(hipMemset(pl->flux, 0, 2 * sizeof(double)), "hipMemset");
+  if (!upload<T>(owner, bcw, bw)) return false;
+  return owner->alloc((void**)flux, 2 * sizeof(double)) && hip_ok(hipMemset(*flux, 0, 2 * sizeof(double)), "hipMemset");
 }
 
-// whether k_i3 keeps the shifted fields in registers for this (precision, P)
 template <typename T>
-bool i3_sreg(int P) {
-  switch (P) {
-    case 32: return qb::I3Regs<T, qb::Cfg<T, 32>::E>::SREG;
-    case 64: return qb::I3Regs<T, qb::Cfg<T, 64>::E>::SREG;
-    default: return qb::I3Regs<T, qb::Cfg<T, 128>::E>::SREG;
-  }
+bool build_bc(qb_plan_s* pl) {
+  return build_bc_for<T>(pl, pl->prob, pl->bl, pl->br, &pl->bcw, &pl->flux);
 }
 
 template <typename T>
 bool build_buffers(qb_plan_s* pl) {
   const qb_problem& p = pl->prob;
-  const size_t FSZ = (size_t)pl->P * pl->P, C = p.Nx, J = p.J;
-  const size_t st = (size_t)4 * C * p.N * p.N * sizeof(T);
-  if (!i3_sreg<T>(pl->P) && !pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T))) return false;
+  const size_t FSZ = (size_t)pl->P * pl->P, C = pl->wcells, J = p.J;
+  const size_t st = (size_t)4 * p.Nx * p.N * p.N * sizeof(T);
+  if (!pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T))) return false;
   return pl->alloc(&pl->spec, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->wP, C * 5 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->terms, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->acc, C * 14 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3sum, C * 4 * FSZ * sizeof(T)) &&
@@ -331,9 +378,8 @@ bool build_buffers(qb_plan_s* pl) {
 template <typename T>
 bool build_adjoint(qb_plan_s* pl) {
   const qb_problem& p = pl->prob;
-  const size_t FSZ = (size_t)pl->P * pl->P, C = p.Nx, J = p.J, b = sizeof(T);
-  const size_t st = (size_t)4 * C * p.N * p.N * b;
-  if (!pl->i3s && !pl->alloc(&pl->i3s, C * J * 4 * FSZ * b)) return false;
+  const size_t FSZ = (size_t)pl->P * pl->P, C = pl->wcells, J = p.J, b = sizeof(T);
+  const size_t st = (size_t)4 * p.Nx * p.N * p.N * b;
   void** states[] = {&pl->wn, &pl->wa, &pl->w1, &pl->wb, &pl->lb, &pl->ls, &pl->la, &pl->cg, &pl->g0};
   for (void** q : states)
     if (!pl->alloc(q, st)) return false;
@@ -341,7 +387,7 @@ bool build_adjoint(qb_plan_s* pl) {
          pl->alloc(&pl->gspec, C * 22 * FSZ * b) && pl->alloc(&pl->gf0, C * 7 * FSZ * b) &&
          pl->alloc(&pl->tsb, C * 16 * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
          pl->alloc(&pl->i3sb, C * J * 4 * FSZ * b) && pl->alloc(&pl->gsum, C * 8 * FSZ * b) &&
-         pl->alloc(&pl->ext, (size_t)4 * (C + 4) * p.N * p.N * b) &&
+         pl->alloc(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
          pl->alloc((void**)&pl->lflux, 2 * sizeof(double));
 }
 
@@ -354,13 +400,14 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.M = pl->prob.M;
   d.P = pl->P;
   d.L = (T)pl->prob.L;
-  d.tw = (const T*)pl->tw;
-  d.phip = (const T*)pl->phip;
-  d.Kt = (const T*)pl->Kt;
-  d.psi = (const T*)pl->psi;
-  d.psip = (const T*)pl->psip;
-  d.psiw = (const T*)pl->psiw;
-  d.psips = (const T*)pl->psips;
+  const qb_plan_s::TabSet& ts = pl->tabs[pl->cur_tab];
+  d.tw = (const T*)ts.tw;
+  d.phip = (const T*)ts.phip;
+  d.Kt = (const T*)ts.Kt;
+  d.psi = (const T*)ts.psi;
+  d.psip = (const T*)ts.psip;
+  d.psiw = (const T*)ts.psiw;
+  d.psips = (const T*)ts.psips;
   d.phx = (const T*)pl->phx;
   d.phy = (const T*)pl->phy;
   d.wm = (const T*)pl->wm;
@@ -385,13 +432,14 @@ DevPlan<T> devplan(qb_plan_s* pl) {
 int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 // C[w] for cells [0, ncells) of the Pauli state w -> c (both [4][Nx][N][N])
-template <typename T, int P>
-bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
-  constexpr int E = qb::Cfg<T, P>::E;
+// C[w] for the cells [cell0, cell0 + ncells) of the state arrays w, c
+// (ncells <= wcells; the workspace holds the chunk's cells from index 0)
+template <typename T, int P, int E>
+bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s) {
   constexpr int NT = qb::Fft2<T, P, E>::NT;
   DevPlan<T> d = devplan<T>(pl);
   int id = pl->begin(QB_K_DFT_IN, s);
-  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, 0);
+  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
   id = pl->begin(QB_K_TERMS, s);
   hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
@@ -402,30 +450,75 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t
   const size_t nel = (size_t)ncells * P * P;
   hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
   id = pl->begin(QB_K_COMBINE, s);
-  hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, 0);
+  hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, cell0);
   pl->end(id, s);
   return hip_ok(hipGetLastError(), "collision launch");
 }
 
+// Tile shapes (elements per thread E; lanes per line P / E) compiled for
+// each padded grid size; the first is the default, qb_plan_tune picks one.
+std::vector<int> tile_candidates(int P) {
+  switch (P) {
+    case 32: return {16, 8};
+    case 64: return {32, 16};
+    default: return {32};
+  }
+}
+
 template <typename T>
-bool collision_any(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
+bool collision_chunk(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s) {
   switch (pl->P) {
-    case 32: return collision_pipeline<T, 32>(pl, w, c, ncells, s);
-    case 64: return collision_pipeline<T, 64>(pl, w, c, ncells, s);
-    case 128: return collision_pipeline<T, 128>(pl, w, c, ncells, s);
+    case 32:
+      return pl->E == 8 ? collision_pipeline<T, 32, 8>(pl, w, c, ncells, cell0, s)
+                        : collision_pipeline<T, 32, 16>(pl, w, c, ncells, cell0, s);
+    case 64:
+      return pl->E == 16 ? collision_pipeline<T, 64, 16>(pl, w, c, ncells, cell0, s)
+                         : collision_pipeline<T, 64, 32>(pl, w, c, ncells, cell0, s);
+    case 128: return collision_pipeline<T, 128, 32>(pl, w, c, ncells, cell0, s);
   }
   return false;
 }
 
+// C[w] for cells [0, ncells), in chunks of at most wcells cells
+template <typename T>
+bool collision_any(qb_plan_s* pl, const T* w, T* c, int ncells, hipStream_t s) {
+  for (int c0 = 0; c0 < ncells; c0 += pl->wcells)
+    if (!collision_chunk<T>(pl, w, c, std::min(pl->wcells, ncells - c0), c0, s)) return false;
+  return true;
+}
+
+// Boundary data of one problem's cells inside a state array: the first
+// cell, the cell count, the walls and their device tables.
+struct Segment {
+  int offset, Nx;
+  qb::BcDev bl, br;
+  const void* bcw;
+  double* flux;
+  bool left_maxwell, right_maxwell;
+};
+
+Segment whole(qb_plan_s* pl) {
+  const qb_problem& p = pl->prob;
+  return Segment{0, p.Nx, pl->bl, pl->br, pl->bcw, pl->flux, p.left.kind == QB_MAXWELL, p.right.kind == QB_MAXWELL};
+}
+
+// tmp = T(dt) cur on one segment; arrays hold `ntot` cells per component
+template <typename T>
+void transport_seg(qb_plan_s* pl, const T* cur, T* tmp, double dt, const Segment& g, int ntot, hipStream_t s) {
+  const int N = pl->prob.N;
+  const size_t per = (size_t)N * N, n = (size_t)g.Nx * per, off = (size_t)g.offset * per;
+  const int lm = g.left_maxwell, rm = g.right_maxwell;
+  if (lm || rm)
+    hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur + off, g.flux, g.Nx, N, pl->prob.L, lm,
+                       rm);
+  hipLaunchKernelGGL((qb::k_transport<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur + off, tmp + off,
+                     (const T*)g.bcw, g.flux, g.bl, g.br, (T)dt, g.Nx, N, (T)pl->prob.L, ntot);
+}
+
 template <typename T>
 bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
-  const qb_problem& p = pl->prob;
-  const size_t n = (size_t)p.Nx * p.N * p.N;
-  const int lm = p.left.kind == QB_MAXWELL, rm = p.right.kind == QB_MAXWELL;
   const int id = pl->begin(QB_K_TRANSPORT, s);
-  if (lm || rm) hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur, pl->flux, p.Nx, p.N, p.L, lm, rm);
-  hipLaunchKernelGGL((qb::k_transport<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, tmp, (const T*)pl->bcw,
-                     pl->flux, pl->bl, pl->br, (T)dt, p.Nx, p.N, (T)p.L);
+  transport_seg<T>(pl, cur, tmp, dt, whole(pl), pl->prob.Nx, s);
   pl->end(id, s);
   std::swap(cur, tmp);
   return hip_ok(hipGetLastError(), "transport launch");
@@ -441,19 +534,19 @@ bool transport_to(qb_plan_s* pl, const T* src, T* dst, double dt, hipStream_t s)
 
 // ------------------------------------------------------------------ adjoint pipelines
 // out = C'(w)^T lam for cells [0, ncells) (Pauli state layout, gradients)
-template <typename T, int P>
-bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, hipStream_t s) {
-  constexpr int E = qb::Cfg<T, P>::E;
+template <typename T, int P, int E>
+bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, int cell0,
+                            hipStream_t s) {
   constexpr int NT = qb::Fft2<T, P, E>::NT;
   DevPlan<T> d = devplan<T>(pl);
   int id = pl->begin(QB_K_DFT_IN, s);
-  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, 0);
+  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
   id = pl->begin(QB_K_TERMS, s);
   hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
   pl->end(id, s);
   id = pl->begin(QB_K_ADJOINT, s);
-  hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, 0);
+  hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, cell0);
   const size_t nel = (size_t)ncells * P * P;
   hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
   hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
@@ -463,19 +556,30 @@ bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int
   pl->end(id, s);
   id = pl->begin(QB_K_ADJOINT, s);
   hipLaunchKernelGGL((qb::k_grad_pre<T>), dim3(blocks(nel * 8, 256)), dim3(256), 0, s, d, ncells, P * P);
-  hipLaunchKernelGGL((qb::k_grad_out<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, out, 0);
+  hipLaunchKernelGGL((qb::k_grad_out<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, out, cell0);
   pl->end(id, s);
   return hip_ok(hipGetLastError(), "collision adjoint launch");
 }
 
 template <typename T>
-bool collision_vjp_any(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, hipStream_t s) {
+bool collision_vjp_chunk(qb_plan_s* pl, const T* w, const T* lam, T* out, int n, int c0, hipStream_t s) {
   switch (pl->P) {
-    case 32: return collision_vjp_pipeline<T, 32>(pl, w, lam, out, ncells, s);
-    case 64: return collision_vjp_pipeline<T, 64>(pl, w, lam, out, ncells, s);
-    case 128: return collision_vjp_pipeline<T, 128>(pl, w, lam, out, ncells, s);
+    case 32:
+      return pl->E == 8 ? collision_vjp_pipeline<T, 32, 8>(pl, w, lam, out, n, c0, s)
+                        : collision_vjp_pipeline<T, 32, 16>(pl, w, lam, out, n, c0, s);
+    case 64:
+      return pl->E == 16 ? collision_vjp_pipeline<T, 64, 16>(pl, w, lam, out, n, c0, s)
+                         : collision_vjp_pipeline<T, 64, 32>(pl, w, lam, out, n, c0, s);
+    case 128: return collision_vjp_pipeline<T, 128, 32>(pl, w, lam, out, n, c0, s);
   }
   return false;
+}
+
+template <typename T>
+bool collision_vjp_any(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, hipStream_t s) {
+  for (int c0 = 0; c0 < ncells; c0 += pl->wcells)
+    if (!collision_vjp_chunk<T>(pl, w, lam, out, std::min(pl->wcells, ncells - c0), c0, s)) return false;
+  return true;
 }
 
 // out = T'(x)^T lam for one transport step of length dt taken at state x
@@ -686,6 +790,64 @@ qb_status do_adjoint_step(qb_plan_s* pl, const void* W, const void* record, cons
   return from_cot<T>(pl, g0, lam, p.Nx, s) ? QB_OK : QB_EHIP;
 }
 
+// ------------------------------------------------------------------ tuning
+// Time the collision pipeline on `ncells` cells for every tile shape of the
+// plan's padded grid and keep the fastest; choices are cached per (precision,
+// N, J, M, ncells) for the life of the process.
+struct TuneKey {
+  int precision, N, J, M, ncells;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(precision, N, J, M, ncells) < std::tie(o.precision, o.N, o.J, o.M, o.ncells);
+  }
+};
+std::map<TuneKey, int>& tune_cache() {
+  static std::map<TuneKey, int> m;
+  return m;
+}
+
+template <typename T>
+qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const std::vector<int> cands = tile_candidates(pl->P);
+  const TuneKey key{p.precision, p.N, p.J, p.M, ncells};
+  auto it = tune_cache().find(key);
+  int best = cands[0];
+  if (it != tune_cache().end()) {
+    best = it->second;
+  } else if (cands.size() > 1) {
+    T* w = (T*)pl->st0;
+    T* c = (T*)pl->cbuf;
+    if (!hip_ok(hipMemsetAsync(w, 0, (size_t)4 * p.Nx * p.N * p.N * sizeof(T), s), "hipMemsetAsync"))
+      return QB_EHIP;
+    const bool prof = pl->profiling;
+    pl->profiling = false;
+    hipEvent_t a = pl->event(), b = pl->event();
+    float best_ms = 1e30f;
+    for (int E : cands) {
+      if (!select_tile<T>(pl, E)) return QB_EHIP;
+      if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;  // warm-up
+      (void)hipEventRecord(a, s);
+      for (int r = 0; r < 2; ++r)
+        if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;
+      (void)hipEventRecord(b, s);
+      if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = E;
+      }
+    }
+    pl->pool.push_back(a);
+    pl->pool.push_back(b);
+    pl->profiling = prof;
+    tune_cache()[key] = best;
+  }
+  if (!select_tile<T>(pl, best)) return QB_EHIP;
+  if (chosen) *chosen = best;
+  return QB_OK;
+}
+
 qb_status validate_bc(const qb_bc& b) {
   if (b.kind != QB_PERIODIC && b.kind != QB_DIRICHLET && b.kind != QB_MAXWELL) return QB_EINVAL;
   if (b.kind == QB_MAXWELL && !(b.alpha >= 0.0 && b.alpha <= 1.0)) return QB_EINVAL;
@@ -707,6 +869,154 @@ qb_status validate(const qb_problem* p) {
   return QB_OK;
 }
 
+// Largest number of cells one collision launch covers: the workspace
+// (about (41 + 8 J) P^2 scalars per cell) is sized for this many.
+constexpr int kChunkCells = 512;
+
+qb_plan_s* create_plan(const qb_problem& problem) {
+  qb_plan_s* pl = new qb_plan_s();
+  pl->prob = problem;
+  pl->P = 2 * problem.N;
+  pl->E = cfg_E(problem.precision, pl->P);
+  pl->TPR = pl->P / pl->E;
+  pl->NT = pl->P * pl->TPR;
+  pl->wcells = std::min(problem.Nx, kChunkCells);
+  bool ok;
+  if (problem.precision == QB_F64)
+    ok = build_tables<double>(pl) && build_bc<double>(pl) && build_buffers<double>(pl);
+  else
+    ok = build_tables<float>(pl) && build_bc<float>(pl) && build_buffers<float>(pl);
+  if (!ok) {
+    delete pl;
+    return nullptr;
+  }
+  return pl;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ batches
+// Independent problems grouped by velocity grid N: the cells of a group are
+// concatenated in one state array and every collision kernel runs once over
+// all of them; transport runs per problem on its segment of the array.
+struct qb_batch_s {
+  int precision = QB_F64;
+  std::vector<qb_problem> probs;
+  struct Group {
+    qb_plan_s* plan = nullptr;
+    std::vector<int> members;
+    std::vector<Segment> segs;
+    int total = 0;
+    double* B = nullptr;    // [total][3]
+    double* mom = nullptr;  // [mom_cap][total][7]
+    int mom_cap = 0;
+  };
+  std::vector<Group> groups;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uintptr_t> key;
+  size_t bytes() const {
+    size_t b = 0;
+    for (const Group& g : groups) b += g.plan->bytes;
+    return b;
+  }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+  ~qb_batch_s() {
+    (void)hipDeviceSynchronize();
+    drop_graph();
+    if (cap) (void)hipStreamDestroy(cap);
+    for (Group& g : groups) delete g.plan;
+  }
+};
+
+namespace {
+
+template <typename T>
+bool batch_enqueue(qb_batch_s* b, void* const* W, const double* const* B, double dt, int nsteps,
+                   double* const* mom, hipStream_t s) {
+  for (qb_batch_s::Group& g : b->groups) {
+    qb_plan_s* pl = g.plan;
+    const int N = pl->prob.N, ntot = g.total;
+    const size_t per = (size_t)N * N, n = (size_t)ntot * per;
+    T* cur = (T*)pl->st0;
+    T* tmp = (T*)pl->st2;
+    T* w1 = (T*)pl->st1;
+    T* c = (T*)pl->cbuf;
+    bool any_mom = false;
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const int m = g.members[k];
+      const Segment& sg = g.segs[k];
+      if (!to_state<T, T>(pl, W[m], cur + (size_t)sg.offset * per, sg.Nx, s)) return false;
+      hipLaunchKernelGGL(qb::k_copy_f64, dim3(blocks((size_t)sg.Nx * 3, 256)), dim3(256), 0, s, B ? B[m] : nullptr,
+                         g.B + (size_t)sg.offset * 3, sg.Nx * 3);
+      any_mom = any_mom || (mom && mom[m]);
+    }
+    const size_t mstride = (size_t)ntot * 7;
+    if (any_mom && !moments<T>(pl, cur, g.mom, s)) return false;
+    auto half = [&](T*& a, T*& t) {
+      const int id = pl->begin(QB_K_TRANSPORT, s);
+      for (const Segment& sg : g.segs) transport_seg<T>(pl, a, t, 0.5 * dt, sg, ntot, s);
+      pl->end(id, s);
+      std::swap(a, t);
+      return hip_ok(hipGetLastError(), "transport launch");
+    };
+    for (int it = 0; it < nsteps; ++it) {
+      if (!half(cur, tmp)) return false;
+      if (!collision_any<T>(pl, cur, c, ntot, s)) return false;
+      int id = pl->begin(QB_K_HEUN, s);
+      hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, g.B, (T)dt, ntot, N, 1);
+      pl->end(id, s);
+      if (!collision_any<T>(pl, w1, c, ntot, s)) return false;
+      id = pl->begin(QB_K_HEUN, s);
+      hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, g.B, (T)dt, ntot, N, 2);
+      pl->end(id, s);
+      if (!half(cur, tmp)) return false;
+      if (any_mom && !moments<T>(pl, cur, g.mom + (it + 1) * mstride, s)) return false;
+    }
+    for (size_t k = 0; k < g.members.size(); ++k) {
+      const int m = g.members[k];
+      const Segment& sg = g.segs[k];
+      if (!from_state<T, T>(pl, cur + (size_t)sg.offset * per, W[m], sg.Nx, s)) return false;
+      if (mom && mom[m])
+        hipLaunchKernelGGL(qb::k_scatter_moments, dim3(blocks((size_t)(nsteps + 1) * sg.Nx * 7, 256)), dim3(256), 0,
+                           s, (const double*)g.mom, mom[m], nsteps + 1, ntot, sg.offset, sg.Nx);
+    }
+    if (!hip_ok(hipGetLastError(), "batch launch")) return false;
+  }
+  return true;
+}
+
+template <typename T>
+qb_status batch_build(qb_batch_s* b) {
+  for (qb_batch_s::Group& g : b->groups) {
+    qb_problem gp = b->probs[g.members[0]];
+    gp.Nx = g.total;
+    gp.left.kind = QB_PERIODIC;
+    gp.right.kind = QB_PERIODIC;
+    g.plan = create_plan(gp);
+    if (!g.plan) return QB_EHIP;
+    int off = 0;
+    for (int m : g.members) {
+      const qb_problem& p = b->probs[m];
+      Segment sg{off, p.Nx, {}, {}, nullptr, nullptr, p.left.kind == QB_MAXWELL, p.right.kind == QB_MAXWELL};
+      void* bcw = nullptr;
+      if (!build_bc_for<T>(g.plan, p, sg.bl, sg.br, &bcw, &sg.flux)) return QB_EHIP;
+      sg.bcw = bcw;
+      g.segs.push_back(sg);
+      off += p.Nx;
+    }
+    if (!g.plan->alloc((void**)&g.B, (size_t)g.total * 3 * sizeof(double))) return QB_EHIP;
+  }
+  return QB_OK;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ C ABI
@@ -717,21 +1027,8 @@ qb_status qb_plan_create(const qb_problem* problem, qb_plan* out) {
   *out = nullptr;
   qb_status st = validate(problem);
   if (st != QB_OK) return st;
-  qb_plan_s* pl = new qb_plan_s();
-  pl->prob = *problem;
-  pl->P = 2 * problem->N;
-  pl->E = cfg_E(problem->precision, pl->P);
-  pl->TPR = pl->P / pl->E;
-  pl->NT = pl->P * pl->TPR;
-  bool ok;
-  if (problem->precision == QB_F64)
-    ok = build_tables<double>(pl) && build_bc<double>(pl) && build_buffers<double>(pl);
-  else
-    ok = build_tables<float>(pl) && build_bc<float>(pl) && build_buffers<float>(pl);
-  if (!ok) {
-    delete pl;
-    return QB_EHIP;
-  }
+  qb_plan_s* pl = create_plan(*problem);
+  if (!pl) return QB_EHIP;
   *out = pl;
   return QB_OK;
 }
@@ -887,6 +1184,146 @@ qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_
   return QB_OK;
 }
 
-int32_t qb_version(void) { return 200; }
+qb_status qb_plan_set_tile(qb_plan plan, int32_t E) {
+  if (!plan) return QB_EINVAL;
+  const std::vector<int> c = tile_candidates(plan->P);
+  if (std::find(c.begin(), c.end(), (int)E) == c.end()) return QB_ENOTSUP;
+  const bool ok = plan->prob.precision == QB_F64 ? select_tile<double>(plan, E) : select_tile<float>(plan, E);
+  return ok ? QB_OK : QB_EHIP;
+}
+
+qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream) {
+  if (!plan || ncells < 1) return QB_EINVAL;
+  if (ncells > plan->prob.Nx) return QB_EWORKSPACE;
+  int chosen = 0;
+  hipStream_t s = (hipStream_t)stream;
+  const qb_status st = plan->prob.precision == QB_F64 ? do_tune<double>(plan, ncells, &chosen, s)
+                                                      : do_tune<float>(plan, ncells, &chosen, s);
+  if (st == QB_OK && tile) *tile = chosen;
+  return st;
+}
+
+qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, qb_batch* out) {
+  if (!out || !problems || nprob < 1) return QB_EINVAL;
+  *out = nullptr;
+  const qb_problem& p0 = problems[0];
+  for (int i = 0; i < nprob; ++i) {
+    const qb_problem& p = problems[i];
+    const qb_status st = validate(&p);
+    if (st != QB_OK) return st;
+    if (p.precision != p0.precision || p.J != p0.J || p.L != p0.L || p.R != p0.R) return QB_EINVAL;
+  }
+  qb_batch_s* b = new qb_batch_s();
+  b->precision = p0.precision;
+  b->probs.assign(problems, problems + nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const qb_problem& p = problems[i];
+    qb_batch_s::Group* g = nullptr;
+    for (auto& x : b->groups)
+      if (b->probs[x.members[0]].N == p.N) g = &x;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+    } else if (b->probs[g->members[0]].M != p.M) {
+      delete b;
+      return QB_EINVAL;
+    }
+    g->members.push_back(i);
+    g->total += p.Nx;
+  }
+  const qb_status st = b->precision == QB_F64 ? batch_build<double>(b) : batch_build<float>(b);
+  if (st != QB_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return QB_OK;
+}
+
+qb_status qb_batch_destroy(qb_batch batch) {
+  if (!batch) return QB_EINVAL;
+  delete batch;
+  return QB_OK;
+}
+
+size_t qb_batch_bytes(qb_batch batch) { return batch ? batch->bytes() : 0; }
+
+qb_status qb_batch_tune(qb_batch batch, void* stream) {
+  if (!batch) return QB_EINVAL;
+  for (auto& g : batch->groups) {
+    const int n = std::min(g.total, g.plan->wcells);
+    const qb_status st = qb_plan_tune(g.plan, n, nullptr, stream);
+    if (st != QB_OK) return st;
+  }
+  batch->drop_graph();  // recorded launches refer to the previous tiles
+  return QB_OK;
+}
+
+qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, double dt, int32_t nsteps,
+                        double* const* moments, int32_t flags, void* stream) {
+  if (!batch || !W || nsteps < 0 || !(dt >= 0.0) || !std::isfinite(dt)) return QB_EINVAL;
+  const int np = (int)batch->probs.size();
+  for (int m = 0; m < np; ++m) {
+    const qb_problem& p = batch->probs[m];
+    if (!W[m]) return QB_EINVAL;
+    if (0.5 * dt * p.L * p.Nx > 1.0 + 1e-12) return QB_ECFL;
+  }
+  bool any_mom = false;
+  for (int m = 0; moments && m < np; ++m) any_mom = any_mom || moments[m];
+  // moments scratch (grows outside any capture)
+  for (auto& g : batch->groups) {
+    if (any_mom && nsteps + 1 > g.mom_cap) {
+      if (!g.plan->alloc((void**)&g.mom, (size_t)(nsteps + 1) * g.total * 7 * sizeof(double))) return QB_EHIP;
+      g.mom_cap = nsteps + 1;
+      batch->drop_graph();
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto run = [&](hipStream_t q) {
+    return batch->precision == QB_F64 ? batch_enqueue<double>(batch, W, B, dt, nsteps, moments, q)
+                                      : batch_enqueue<float>(batch, W, B, dt, nsteps, moments, q);
+  };
+  if (!(flags & QB_BATCH_GRAPH)) return run(s) ? QB_OK : QB_EHIP;
+  // graph replay: one recorded launch sequence per argument set
+  std::vector<uintptr_t> key;
+  for (int m = 0; m < np; ++m) {
+    key.push_back((uintptr_t)W[m]);
+    key.push_back((uintptr_t)(B ? B[m] : nullptr));
+    key.push_back((uintptr_t)(moments ? moments[m] : nullptr));
+  }
+  uint64_t dbits;
+  std::memcpy(&dbits, &dt, sizeof dbits);
+  key.push_back((uintptr_t)dbits);
+  key.push_back((uintptr_t)nsteps);
+  if (!batch->exec || key != batch->key) {
+    batch->drop_graph();
+    if (!batch->cap && !hip_ok(hipStreamCreateWithFlags(&batch->cap, hipStreamNonBlocking), "hipStreamCreate"))
+      return QB_EHIP;
+    std::vector<bool> prof;
+    for (auto& g : batch->groups) {
+      prof.push_back(g.plan->profiling);
+      g.plan->profiling = false;
+    }
+    if (!hip_ok(hipStreamBeginCapture(batch->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
+      return QB_EHIP;
+    const bool ok = run(batch->cap);
+    hipGraph_t graph = nullptr;
+    const bool ended = hip_ok(hipStreamEndCapture(batch->cap, &graph), "hipStreamEndCapture");
+    for (size_t i = 0; i < batch->groups.size(); ++i) batch->groups[i].plan->profiling = prof[i];
+    if (!ok || !ended) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return QB_EHIP;
+    }
+    batch->graph = graph;
+    if (!hip_ok(hipGraphInstantiate(&batch->exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+      batch->drop_graph();
+      return QB_EHIP;
+    }
+    batch->key = key;
+  }
+  return hip_ok(hipGraphLaunch(batch->exec, s), "hipGraphLaunch") ? QB_OK : QB_EHIP;
+}
+
+int32_t qb_version(void) { return 300; }
 
 }  // extern "C"
