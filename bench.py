@@ -119,6 +119,45 @@ def run_adjoint(steps, every):
             "grad_norms": {"W0": float(Wr.grad.abs().max()), "B": float(Br.grad.abs().max())}}
 
 
+def run_batch(steps, nprob):
+    """Batched throughput on the uneven-batch workload (64 periodic problems,
+    Nx ~ U{32, 64, 128, 256, 512}, N ~ U{32, 64}, J = 32, M = N, B = 0,
+    dt = 2.5e-4, float32 with float64 moments): tile autotuning, then one
+    `steps`-step call recorded as a HIP graph and launched (the timed region
+    includes the host-side recording, a few milliseconds); the N = 64
+    problems alone are timed as a second batch.  The kernels are already
+    loaded by the earlier measurements."""
+    import torch
+    import paper_1408_1782_amd as qb
+    import workloads
+
+    wls = workloads.batch_config(nprob, steps)
+
+    def one(sel, label):
+        probs = [qb.Problem(w.Nx, w.N, w.J, w.M, w.L, w.R, "f32") for w in sel]
+        batch = qb.Batch(probs)
+        batch.tune()
+        Ws = [torch.from_numpy(w.W0).to(torch.complex64).cuda().contiguous() for w in sel]
+        moms = [torch.zeros((steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda") for w in sel]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batch.step(Ws, None, wls[0].dt, steps, moms, graph=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        cells = sum(w.Nx for w in sel)
+        log(f"[batch {label}] {len(sel)} problems, {cells} cells, {steps} step(s) in {t:.3f} s")
+        finite = all(bool(torch.isfinite(torch.view_as_real(W)).all()) for W in Ws)
+        batch.close()
+        return {"problems": len(sel), "cells": cells, "seconds": t, "value": cells * steps / t,
+                "finite": finite}
+
+    full = one(wls, "all")
+    sub = one([w for w in wls if w.N == 64], "N=64")
+    return {"workload": "uneven_batch", "unit": "cells*steps/s", "dtype": "f32", "steps": steps,
+            "graph": True, "all": full, "N64": sub,
+            "N32_cells": sum(w.Nx for w in wls if w.N == 32)}
+
+
 def cpu_baseline(wl):
     """The CPU oracle on a bounded sample of the same workload: one collision
     evaluation of one cell plus one transport half-step over all cells."""
@@ -171,6 +210,9 @@ def main():
     ap.add_argument("--adj-steps", type=int, default=40,
                     help="steps of the adjoint/forward measurement (0 skips it)")
     ap.add_argument("--adj-every", type=int, default=20, help="checkpoint interval of the adjoint run")
+    ap.add_argument("--batch-steps", type=int, default=1,
+                    help="steps of the uneven-batch measurement (0 skips it)")
+    ap.add_argument("--batch-problems", type=int, default=64, help="problems in the uneven batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -223,6 +265,8 @@ def main():
         adj = run_adjoint(args.adj_steps, args.adj_every)
         out["adjoint_forward_ratio"] = adj["ratio"]
         out["adjoint"] = adj
+    if args.batch_steps > 0:
+        out["batched"] = run_batch(args.batch_steps, args.batch_problems)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

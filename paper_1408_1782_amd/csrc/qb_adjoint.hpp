@@ -61,7 +61,8 @@ __global__ void k_cot_to_api(const T* __restrict__ g, TA* __restrict__ G, int nc
 // Transpose of k_combine: the map r -> c is E . Proj with Proj the real,
 // symmetric band projection inv2 . (mask / P^2) . fwd2 and E the restriction
 // to the even points, so the cotangent of the assembled fields is
-// Proj(E^T lam): lam placed on the even points, projected onto Xi.
+// Proj(E^T lam): lam placed on the even points, projected onto Xi.  Its
+// spectrum (packed pairs (0 + i1), (2 + i3), col spec) goes to lamh.
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_lam_in(DevPlan<T> d, const T* __restrict__ lam,
                                                                 int cell0) {
@@ -76,6 +77,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_lam_in(DevPlan<T> d, co
   const unsigned vo = threadIdx.x * S;
   const size_t cs = (size_t)d.Nx * N * N;
   const rsrc_t ro = mkbuf(d.lamP + (size_t)lc * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rh = mkbuf(d.lamh + (size_t)lc * 4 * K::FSZ, 4 * K::FSZ);
   const int y = eng.line;
   const bool on_grid = ((eng.q | y) & 1) == 0;
   const int bx = centered<P>(eng.line);
@@ -99,6 +101,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_lam_in(DevPlan<T> d, co
       const bool in = kx_in && by > -N / 2 && by < N / 2;
       zr[k] = in ? zr[k] * sc : (T)0;
       zi[k] = in ? zi[k] * sc : (T)0;
+      // spectrum of the projected cotangent (packed pair), kept for k_i3_vjp
+      bst<T>(rh, zr[k], vo, ((2 * pr) * K::FSZ + k * K::NT) * S);
+      bst<T>(rh, zi[k], vo, ((2 * pr + 1) * K::FSZ + k * K::NT) * S);
     }
     eng.inv2(zr, zi);
 #pragma unroll
@@ -310,14 +315,22 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
 }
 
 // ------------------------------------------------------------------ I_3
-// Transpose of k_i3, one workgroup per (cell, j), loop over m.  With
-// s_nu = inv2(phase w_hat_nu), Psi(x) = inv2(psi'_j / P^2 fwd2(x)) (real,
-// symmetric), c = (pi/J) w_m and b_bar the cotangent of the I_3 sums:
-//   forward   b_nu += c sum_mu eta_mu s_mu Psi(w_mu s_nu)
-//   reverse   s_bar_mu  += c eta_mu sum_nu b_bar_nu Psi(w_mu s_nu)          (shifted factor)
-//             w_bar_mu  += c eta_mu sum_nu s_nu Psi(b_bar_nu s_mu)          (w inside Psi)
-//             s_bar_nu  += c sum_mu eta_mu w_mu Psi(b_bar_nu s_mu)          (shifted field inside Psi)
-//             w_hat_bar += phase conj(F) s_bar                              (per m)
+// Transpose of k_i3, one workgroup per (cell, j), Gauss-Legendre nodes in
+// symmetric pairs (m, m' = M-1-m; the middle node of an odd M alone).
+// With S the shift of node m, s_nu = S w_nu, t_nu = S b_bar_nu (b_bar the
+// cotangent of the I_3 sums, b_bar_0 = -2 pi lam_0, b_bar_k = 2 pi lam_k),
+// Psi = inv2(psi'_j / P^2 fwd2(.)) (real, symmetric), c = (pi/J) w_m,
+// q_a,nu = Psi(w_a s_nu), r_a,nu = Psi(b_bar_nu s_a), u_a,nu = Psi(t_nu w_a):
+//   node m :  Y_a     += c eta_a sum_nu b_bar_nu q_a,nu      (shifted factor)
+//             w_bar_a += c eta_a sum_nu s_nu r_a,nu          (w inside Psi)
+//             Y_nu    += c sum_a eta_a w_a r_a,nu            (shifted field inside Psi)
+//   node m':  w_bar_nu += c eta_nu sum_a t_a q_a,nu
+//             Y_a     += c eta_a sum_nu w_nu u_a,nu
+//             w_bar_nu += c sum_a eta_a s_a u_a,nu
+//   w_hat_bar += phase conj(F) Y      (Y = S-transposed part, per node pair)
+// (node m' terms follow from S^{-1} = S^T, translation invariance of Psi
+// and S(f g) = S f S g on the padded grid).  Per pair: 4 shift transforms,
+// 3 x 8 packed convolutions of 2 transforms, 2 final transforms.
 // i3g[cell][j]: [0..3] w_bar (row real), [4..7] w_hat_bar packed as
 // (mu 0 + i mu 1), (mu 2 + i mu 3), re/im planes, col spec.
 template <typename T, int P, int E>
@@ -335,119 +348,167 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp(DevPlan<T> d, in
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
   const rsrc_t rl = mkbuf(d.acot + ((size_t)cell * 16 + 8) * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rh = mkbuf(d.lamh + (size_t)cell * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rg = mkbuf(d.i3g + tb * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rb = mkbuf(d.i3s + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rt = mkbuf(d.i3t + tb * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rc = mkbuf(d.i3sb + tb * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
 #pragma unroll 1
-  for (int m = 0; m < d.M; ++m) {
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int n = 0; n < E; ++n) bst<T>(rg, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+  // one packed convolution Psi(a + i b) of two real fields given elementwise
+  auto conv = [&](T (&zr)[E], T (&zi)[E]) {
+    eng.fwd2(zr, zi);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const T a = bld<T>(rm, vo, (k * K::NT) * S);
+      zr[k] *= a;
+      zi[k] *= a;
+    }
+    eng.inv2(zr, zi);
+  };
+  auto rmw = [&](rsrc_t r, int plane, unsigned o, T v) {
+    const unsigned off = (plane * K::FSZ + o) * S;
+    bst<T>(r, bld<T>(r, vo, off) + v, vo, off);
+  };
+  const int nnode = (d.M + 1) / 2;
+#pragma unroll 1
+  for (int m = 0; m < nnode; ++m) {
+    const bool paired = m != d.M - 1 - m;
     const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
     const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
     const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
-    // shifted fields s_nu
+    // s_nu = S w_nu and (paired) t_nu = S b_bar_nu, two packed shifts each
 #pragma unroll 1
-    for (int pr = 0; pr < 2; ++pr) {
-      const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
-      T zr[E], zi[E];
+    for (int src = 0; src < (paired ? 2 : 1); ++src) {
+#pragma unroll 1
+      for (int pr = 0; pr < 2; ++pr) {
+        T zr[E], zi[E];
 #pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const unsigned o = k * K::NT;
-        T er, ei;
-        cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
-        T ar, ai, br, bi;
-        cmul(bld<T>(rs, vo, (fa + o) * S), bld<T>(rs, vo, (fa + K::FSZ + o) * S), er, ei, ar, ai);
-        cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
-        zr[k] = ar - bi;
-        zi[k] = ai + br;
-      }
-      eng.inv2(zr, zi);
+        for (int k = 0; k < E; ++k) {
+          const unsigned o = k * K::NT;
+          T er, ei;
+          cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
+          if (src == 0) {
+            const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
+            T ar, ai, br, bi;
+            cmul(bld<T>(rs, vo, (fa + o) * S), bld<T>(rs, vo, (fa + K::FSZ + o) * S), er, ei, ar, ai);
+            cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
+            zr[k] = ar - bi;
+            zi[k] = ai + br;
+          } else {
+            cmul(bld<T>(rh, vo, ((2 * pr) * K::FSZ + o) * S), bld<T>(rh, vo, ((2 * pr + 1) * K::FSZ + o) * S), er,
+                 ei, zr[k], zi[k]);
+          }
+        }
+        eng.inv2(zr, zi);
+        // t carries the B-term factors of b_bar: -2 pi (mu = 0), 2 pi (mu > 0)
+        const T fa = src == 0 ? (T)1 : (T)(pr == 0 ? -2.0 * kPi : 2.0 * kPi);
+        const T fb = src == 0 ? (T)1 : (T)(2.0 * kPi);
+        const rsrc_t rd = src == 0 ? rb : rt;
 #pragma unroll
-      for (int n = 0; n < E; ++n) {
-        bst<T>(rb, zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
-        bst<T>(rb, zi[n], vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
+        for (int n = 0; n < E; ++n) {
+          bst<T>(rd, fa * zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
+          bst<T>(rd, fb * zi[n], vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
+        }
       }
     }
-    const T wgt = d.wm[m];
-    // shifted factor: s_bar_mu = c eta_mu sum_nu b_bar_nu Psi(w_mu s_nu)
+    const T c = d.wm[m];
+    // q_a,nu = Psi(w_a s_nu)
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
+      const T cnu = nu == 0 ? c : -c;
 #pragma unroll 1
       for (int mp = 0; mp < 2; ++mp) {
-        const int m0 = 2 * mp, m1 = 2 * mp + 1;
+        const int a0 = 2 * mp, a1 = 2 * mp + 1;
+        const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
           const T sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
-          zr[n] = bld<T>(rw, vo, (m0 * K::FSZ + o) * S) * sv;
-          zi[n] = bld<T>(rw, vo, (m1 * K::FSZ + o) * S) * sv;
+          zr[n] = bld<T>(rw, vo, (a0 * K::FSZ + o) * S) * sv;
+          zi[n] = bld<T>(rw, vo, (a1 * K::FSZ + o) * S) * sv;
         }
-        eng.fwd2(zr, zi);
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const T a = bld<T>(rm, vo, (k * K::NT) * S);
-          zr[k] *= a;
-          zi[k] *= a;
-        }
-        eng.inv2(zr, zi);
-        const T e0 = m0 == 0 ? wgt : -wgt;
+        conv(zr, zi);
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
           const T bb = bld<T>(rl, vo, (nu * K::FSZ + o) * S);
-          T va = e0 * bb * zr[n], vb = -wgt * bb * zi[n];
+          T ya = ca0 * bb * zr[n], yb = ca1 * bb * zi[n];
           if (nu != 0) {
-            va += bld<T>(rc, vo, (m0 * K::FSZ + o) * S);
-            vb += bld<T>(rc, vo, (m1 * K::FSZ + o) * S);
+            ya += bld<T>(rc, vo, (a0 * K::FSZ + o) * S);
+            yb += bld<T>(rc, vo, (a1 * K::FSZ + o) * S);
           }
-          bst<T>(rc, va, vo, (m0 * K::FSZ + o) * S);
-          bst<T>(rc, vb, vo, (m1 * K::FSZ + o) * S);
+          bst<T>(rc, ya, vo, (a0 * K::FSZ + o) * S);
+          bst<T>(rc, yb, vo, (a1 * K::FSZ + o) * S);
+          if (paired) {
+            const T ta = bld<T>(rt, vo, (a0 * K::FSZ + o) * S), tb2 = bld<T>(rt, vo, (a1 * K::FSZ + o) * S);
+            rmw(rg, nu, o, cnu * (ta * zr[n] + tb2 * zi[n]));
+          }
         }
       }
     }
-    // w inside Psi and the shifted field inside Psi: r = Psi(b_bar_nu s_mu)
+    // r_a,nu = Psi(b_bar_nu s_a)
 #pragma unroll 1
     for (int nu = 0; nu < 4; ++nu) {
 #pragma unroll 1
       for (int mp = 0; mp < 2; ++mp) {
-        const int m0 = 2 * mp, m1 = 2 * mp + 1;
+        const int a0 = 2 * mp, a1 = 2 * mp + 1;
+        const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
           const T bb = bld<T>(rl, vo, (nu * K::FSZ + o) * S);
-          zr[n] = bb * bld<T>(rb, vo, (m0 * K::FSZ + o) * S);
-          zi[n] = bb * bld<T>(rb, vo, (m1 * K::FSZ + o) * S);
+          zr[n] = bb * bld<T>(rb, vo, (a0 * K::FSZ + o) * S);
+          zi[n] = bb * bld<T>(rb, vo, (a1 * K::FSZ + o) * S);
         }
-        eng.fwd2(zr, zi);
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const T a = bld<T>(rm, vo, (k * K::NT) * S);
-          zr[k] *= a;
-          zi[k] *= a;
-        }
-        eng.inv2(zr, zi);
-        const T e0 = m0 == 0 ? wgt : -wgt;
-        const bool first = m == 0 && nu == 0;
+        conv(zr, zi);
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
           const T sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
-          T va = e0 * sv * zr[n], vb = -wgt * sv * zi[n];
-          if (!first) {
-            va += bld<T>(rg, vo, (m0 * K::FSZ + o) * S);
-            vb += bld<T>(rg, vo, (m1 * K::FSZ + o) * S);
-          }
-          bst<T>(rg, va, vo, (m0 * K::FSZ + o) * S);
-          bst<T>(rg, vb, vo, (m1 * K::FSZ + o) * S);
-          const T wa = bld<T>(rw, vo, (m0 * K::FSZ + o) * S), wb = bld<T>(rw, vo, (m1 * K::FSZ + o) * S);
-          const unsigned on = (nu * K::FSZ + o) * S;
-          bst<T>(rc, bld<T>(rc, vo, on) + e0 * wa * zr[n] - wgt * wb * zi[n], vo, on);
+          rmw(rg, a0, o, ca0 * sv * zr[n]);
+          rmw(rg, a1, o, ca1 * sv * zi[n]);
+          const T wa = bld<T>(rw, vo, (a0 * K::FSZ + o) * S), wb = bld<T>(rw, vo, (a1 * K::FSZ + o) * S);
+          rmw(rc, nu, o, ca0 * wa * zr[n] + ca1 * wb * zi[n]);
         }
       }
     }
-    // w_hat_bar += phase conj(F)(s_bar), packed pairs (0, 1), (2, 3)
+    // u_a,nu = Psi(t_nu w_a), partner node
+    if (paired) {
+#pragma unroll 1
+      for (int nu = 0; nu < 4; ++nu) {
+#pragma unroll 1
+        for (int mp = 0; mp < 2; ++mp) {
+          const int a0 = 2 * mp, a1 = 2 * mp + 1;
+          const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
+          T zr[E], zi[E];
+#pragma unroll
+          for (int n = 0; n < E; ++n) {
+            const unsigned o = n * K::NT;
+            const T tv = bld<T>(rt, vo, (nu * K::FSZ + o) * S);
+            zr[n] = tv * bld<T>(rw, vo, (a0 * K::FSZ + o) * S);
+            zi[n] = tv * bld<T>(rw, vo, (a1 * K::FSZ + o) * S);
+          }
+          conv(zr, zi);
+#pragma unroll
+          for (int n = 0; n < E; ++n) {
+            const unsigned o = n * K::NT;
+            const T wv = bld<T>(rw, vo, (nu * K::FSZ + o) * S);
+            rmw(rc, a0, o, ca0 * wv * zr[n]);
+            rmw(rc, a1, o, ca1 * wv * zi[n]);
+            const T sa = bld<T>(rb, vo, (a0 * K::FSZ + o) * S), sb = bld<T>(rb, vo, (a1 * K::FSZ + o) * S);
+            rmw(rg, nu, o, ca0 * sa * zr[n] + ca1 * sb * zi[n]);
+          }
+        }
+      }
+    }
+    // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3)
 #pragma unroll 1
     for (int pr = 0; pr < 2; ++pr) {
       T zr[E], zi[E];
@@ -458,7 +519,6 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp(DevPlan<T> d, in
         zi[n] = -bld<T>(rc, vo, ((2 * pr + 1) * K::FSZ + o) * S);
       }
       eng.fwd2(zr, zi);
-      const unsigned fr = (4 + 2 * pr) * K::FSZ, fi = (5 + 2 * pr) * K::FSZ;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
@@ -466,12 +526,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp(DevPlan<T> d, in
         cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
         T xr, xi;
         cmul(zr[k], -zi[k], er, ei, xr, xi);
-        if (m != 0) {
-          xr += bld<T>(rg, vo, (fr + o) * S);
-          xi += bld<T>(rg, vo, (fi + o) * S);
-        }
-        bst<T>(rg, xr, vo, (fr + o) * S);
-        bst<T>(rg, xi, vo, (fi + o) * S);
+        rmw(rg, 4 + 2 * pr, o, xr);
+        rmw(rg, 5 + 2 * pr, o, xi);
       }
     }
   }

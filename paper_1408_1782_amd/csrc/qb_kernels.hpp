@@ -54,7 +54,9 @@ struct DevPlan {
   T* acc;    // [cells][7][2][P*P]  spectral accumulators of the I_1 / I_4 tasks
   T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
   T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
-  T* i3sum;  // [cells][4][P*P]     I_3 summed over j
+  T* i3sum;  // [cells][4][P*P]     assembled real-space fields of C
+  T* i3p;    // [cells][J][4][P*P]  partner-node spectra of I_3 per j (2 packed pairs, re/im, col spec)
+  T* i3ps;   // [cells][4][P*P]     i3p summed over j
   // adjoint work buffers (present once the plan's adjoint is enabled)
   T* lamP;   // [cells][4][P*P]     cotangent of the assembled fields, row real
   T* acot;   // [cells][16][P*P]    assembly cotangents: g (3), y (4), S (1), b (4), w direct (4)
@@ -64,6 +66,8 @@ struct DevPlan {
   T* i3g;    // [cells][J][8][P*P]  I_3 adjoint per (cell, j): w cotangent (4, row real),
              //                     packed w_hat cotangents (2 pairs x re/im, col spec)
   T* i3sb;   // [cells][J][4][P*P]  cotangent of the shifted fields of the current (j, m)
+  T* i3t;    // [cells][J][4][P*P]  shifted cotangents of the I_3 sums for the current (j, m)
+  T* lamh;   // [cells][4][P*P]     spectrum of lamP, packed pairs, col spec
   T* gsum;   // [cells][8][P*P]     gathered cotangents (k_grad_pre)
 };
 
@@ -347,20 +351,33 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
 }
 
 // ------------------------------------------------------------------ I_3
-// One workgroup per (cell, j); loops over the M Gauss-Legendre radii.
-// Per (j, m): shifted fields s_nu = IFFT(exp(i alpha_jm . b) w_hat_nu) (two
-// packed transforms), then for each nu and each pair of mu the packed
-// convolution Phi = IFFT(psi'_j FFT(w_mu s_nu)), and
-//   o_nu += (pi/J) w_m sum_mu eta_mu s_mu Phi_mu,nu.
+// One workgroup per (cell, j); loops over the Gauss-Legendre nodes in
+// symmetric pairs (m, m' = M-1-m), rho_m' = -rho_m, w_m' = w_m (the middle
+// node of an odd M runs alone).  With s_nu = S w_nu the field shifted by
+// node m (S = inv2(exp(i alpha_jm . b) fwd2(.)) / P^2) and the packed
+// convolutions Phi_a,b = Psi(w_a s_b), Psi = inv2(psi'_j / P^2 fwd2(.)):
+//   node m :  o_b  += c sum_a eta_a s_a Phi_a,b                 (real space)
+//   node m':  o'_a  = c S^{-1} sum_b eta_b w_b Phi_a,b
+// because translations commute with Psi and distribute over products whose
+// band stays inside the padded grid; the aliased part of the last product
+// falls outside Xi, which the output keeps.  o' is accumulated as a
+// spectrum, conj(phase) fwd2(sign_a o'_a) with the sign of the B term
+// (-1 for a = 0), packed (0 + i1), (2 + i3), into i3p[cell][j].
+// c = (pi/J) w_m.  Per pair: 2 shift transforms, 8 packed convolutions of 2
+// transforms each, 2 transforms of the partner sums.
 // When the four shifted fields fit in registers next to the working field
-// (SREG), they stay there for the whole (j, m) step; otherwise they go
-// through a per-workgroup buffer in global memory.
+// (SREG), they stay there for the whole node; otherwise they go through a
+// per-workgroup buffer.  The partner sums stay in registers when they fit
+// (PAIR); where they do not (float64 with 32 elements per thread), the
+// kernel runs every node unpaired instead.
 #ifndef QB_I3_SREG_VGPRS
 #define QB_I3_SREG_VGPRS 100
 #endif
 template <typename T, int E>
 struct I3Regs {
   static constexpr bool SREG = 6 * E * (int)sizeof(T) / 4 <= QB_I3_SREG_VGPRS;
+  // node pairing pays only while the partner sums stay in registers
+  static constexpr bool PAIR = 2 * E * (int)sizeof(T) / 4 <= 64;
 };
 
 template <typename T>
@@ -380,15 +397,20 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   const int cell = task / d.J;
   const int j = task % d.J;
   const unsigned vo = threadIdx.x * S;
+  const size_t tb = (size_t)cell * d.J + j;
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
-  const rsrc_t ro = mkbuf(d.i3o + ((size_t)cell * d.J + j) * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rb = mkbuf(SREG ? d.i3o : d.i3s + ((size_t)cell * d.J + j) * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t ro = mkbuf(d.i3o + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rp = mkbuf(d.i3p + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rb = mkbuf(SREG ? d.i3o : d.i3s + tb * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
   T s[SREG ? 4 : 1][SREG ? E : 1];
+  constexpr bool PAIR = I3Regs<T, E>::PAIR;
+  const int nnode = PAIR ? (d.M + 1) / 2 : d.M;
 #pragma unroll 1
-  for (int m = 0; m < d.M; ++m) {
+  for (int m = 0; m < nnode; ++m) {
+    const bool paired = PAIR && m != d.M - 1 - m;
     const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
     const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
     const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
@@ -422,10 +444,17 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
     }
     const T wgt = d.wm[m];
 #pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
+    for (int mp = 0; mp < 2; ++mp) {
+      const int m0 = 2 * mp, m1 = 2 * mp + 1;
+      // partner sums of this pair of rows a = m0, m1 (sign of the B term folded in)
+      T pa[PAIR ? E : 1], pb[PAIR ? E : 1];
+      if constexpr (PAIR) {
+#pragma unroll
+        for (int n = 0; n < E; ++n) pa[n] = pb[n] = 0;
+      }
+      const T sa_sign = m0 == 0 ? (T)-1 : (T)1;
 #pragma unroll 1
-      for (int mp = 0; mp < 2; ++mp) {
-        const int m0 = 2 * mp, m1 = 2 * mp + 1;
+      for (int nu = 0; nu < 4; ++nu) {
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
@@ -450,6 +479,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         eng.inv2(zr, zi);
         const T e0 = m0 == 0 ? wgt : -wgt;
         const bool first = m == 0 && mp == 0;
+        const T ew = nu == 0 ? wgt : -wgt;  // c eta_nu
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
@@ -465,7 +495,46 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           T v = e0 * sa * zr[n] - wgt * sb * zi[n];
           if (!first) v += bld<T>(ro, vo, off);
           bst<T>(ro, v, vo, off);
+          if constexpr (PAIR) {
+            if (paired) {
+              const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
+              pa[PAIR ? n : 0] += sa_sign * wv * zr[n];
+              pb[PAIR ? n : 0] += wv * zi[n];
+            }
+          }
           if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      // spectrum of the partner sums: conj(phase) fwd2(pa + i pb), accumulated
+      const unsigned fr = (2 * mp) * K::FSZ, fi = (2 * mp + 1) * K::FSZ;
+      if (paired) {
+        T zr[E], zi[E];
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          zr[n] = pa[PAIR ? n : 0];
+          zi[n] = pb[PAIR ? n : 0];
+        }
+        eng.fwd2(zr, zi);
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const unsigned o = k * K::NT;
+          T er, ei;
+          cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
+          T xr, xi;
+          cmul(zr[k], zi[k], er, -ei, xr, xi);
+          if (m != 0) {
+            xr += bld<T>(rp, vo, (fr + o) * S);
+            xi += bld<T>(rp, vo, (fi + o) * S);
+          }
+          bst<T>(rp, xr, vo, (fr + o) * S);
+          bst<T>(rp, xi, vo, (fi + o) * S);
+        }
+      } else if (m == 0) {
+        // no partner spectrum (unpaired kernel, or a single node)
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          bst<T>(rp, (T)0, vo, (fr + k * K::NT) * S);
+          bst<T>(rp, (T)0, vo, (fi + k * K::NT) * S);
         }
       }
     }
@@ -474,7 +543,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
 
 // Real-space P-grid fields of C, elementwise: sums the per-j partials of I_3
 // and assembles the Pauli components (C_c + pi (A + B + Cq), see k_combine)
-// into i3sum[cell][mu].
+// into i3sum[cell][mu]; sums the partner-node spectra of I_3 into i3ps.
 template <typename T>
 __global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -482,9 +551,15 @@ __global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
   const size_t cell = idx / fsz, e = idx % fsz;
   const size_t per = (size_t)4 * fsz;
   const T* o3 = d.i3o + cell * d.J * per + e;
-  T b[4] = {0, 0, 0, 0};
+  const T* p3 = d.i3p + cell * d.J * per + e;
+  T b[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
   for (int j = 0; j < d.J; ++j)
-    for (int nu = 0; nu < 4; ++nu) b[nu] += o3[(size_t)j * per + (size_t)nu * fsz];
+    for (int nu = 0; nu < 4; ++nu) {
+      b[nu] += o3[(size_t)j * per + (size_t)nu * fsz];
+      q[nu] += p3[(size_t)j * per + (size_t)nu * fsz];
+    }
+  T* ps = d.i3ps + cell * per + e;
+  for (int nu = 0; nu < 4; ++nu) ps[(size_t)nu * fsz] = q[nu];
   const T* wp = d.wP + cell * 5 * fsz + e;
   const T* tr = d.terms + cell * 8 * fsz + e;
   const T w0 = wp[0], w1 = wp[fsz], w2 = wp[2 * fsz], w3 = wp[3 * fsz];
@@ -503,8 +578,9 @@ __global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
 
 // ------------------------------------------------------------------ combine
 // Transform the assembled real-space P-grid fields of C (Pauli components,
-// k_assemble), keep Xi without its -N/2 rows and columns, and evaluate on
-// the velocity grid:  c[mu][cell][i][j].
+// k_assemble), add the partner-node spectra of I_3 (times 2 pi, the B term
+// with its sign already applied), keep Xi without its -N/2 rows and
+// columns, and evaluate on the velocity grid:  c[mu][cell][i][j].
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T* __restrict__ c, int cell0) {
   using K = Kern<T, P, E>;
@@ -517,6 +593,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T
   const int N = P / 2;
   const unsigned vo = threadIdx.x * S;
   const rsrc_t r3 = mkbuf(d.i3sum + (size_t)lc * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rps = mkbuf(d.i3ps + (size_t)lc * 4 * K::FSZ, 4 * K::FSZ);
   const size_t cs = (size_t)d.Nx * N * N;
 #pragma unroll 1
   for (int pr = 0; pr < 2; ++pr) {
@@ -531,12 +608,15 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T
     const int bx = centered<P>(eng.line);
     const bool kx_in = bx > -N / 2 && bx < N / 2;
     const T sc = (T)1 / (T)(P * P);
+    const T tp = (T)(2.0 * kPi);  // B term of the partner nodes: pi * 2 * (sign folded in)
 #pragma unroll
     for (int k = 0; k < E; ++k) {
+      const unsigned o = k * K::NT;
       const int by = centered<P>(eng.bk(k));
       const bool in = kx_in && by > -N / 2 && by < N / 2;
-      zr[k] = in ? zr[k] * sc : (T)0;
-      zi[k] = in ? zi[k] * sc : (T)0;
+      const T ar = bld<T>(rps, vo, ((2 * pr) * K::FSZ + o) * S), ai = bld<T>(rps, vo, ((2 * pr + 1) * K::FSZ + o) * S);
+      zr[k] = in ? (zr[k] + tp * ar) * sc : (T)0;
+      zi[k] = in ? (zi[k] + tp * ai) * sc : (T)0;
     }
     eng.inv2(zr, zi);
     const int y = eng.line;

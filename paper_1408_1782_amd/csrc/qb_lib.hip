@@ -102,13 +102,13 @@ struct qb_plan_s {
   std::vector<TabSet> tabs;
   int cur_tab = 0;
   void *phx, *phy, *wm;  // natural order, independent of the tile
-  void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum;
+  void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum, *i3p, *i3ps;
   void *st0, *st1, *st2, *cbuf, *bcw;
   double* flux;
   // adjoint workspace (qb_plan_enable_adjoint)
   bool adjoint = false;
   void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
-       *i3sb = nullptr, *gsum = nullptr;
+       *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
   void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
        *cg = nullptr, *g0 = nullptr, *ext = nullptr;
   double* lflux = nullptr;
@@ -268,6 +268,14 @@ bool build_phases(qb_plan_s* pl) {
   }
   std::vector<double> gx, gw;
   gauss_legendre(M, gx, gw);
+  // the I_3 kernel pairs node m with M-1-m: make the symmetry exact
+  for (int m = 0; m < M / 2; ++m) {
+    const double x = 0.5 * (gx[M - 1 - m] - gx[m]), w = 0.5 * (gw[m] + gw[M - 1 - m]);
+    gx[m] = -x;
+    gx[M - 1 - m] = x;
+    gw[m] = gw[M - 1 - m] = w;
+  }
+  if (M % 2 == 1) gx[M / 2] = 0.0;
   std::vector<double> phx((size_t)J * M * P * 2), phy((size_t)J * M * P * 2), wm(M);
   for (int m = 0; m < M; ++m) wm[m] = (M_PI / J) * R * gw[m];
   for (int j = 0; j < J; ++j)
@@ -371,6 +379,8 @@ bool build_buffers(qb_plan_s* pl) {
   return pl->alloc(&pl->spec, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->wP, C * 5 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->terms, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->acc, C * 14 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3sum, C * 4 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->i3p, C * J * 4 * FSZ * sizeof(T)) &&
+         pl->alloc(&pl->i3ps, C * 4 * FSZ * sizeof(T)) &&
          pl->alloc(&pl->st0, st) && pl->alloc(&pl->st1, st) && pl->alloc(&pl->st2, st) &&
          pl->alloc(&pl->cbuf, st);
 }
@@ -387,6 +397,7 @@ bool build_adjoint(qb_plan_s* pl) {
          pl->alloc(&pl->gspec, C * 22 * FSZ * b) && pl->alloc(&pl->gf0, C * 7 * FSZ * b) &&
          pl->alloc(&pl->tsb, C * 16 * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
          pl->alloc(&pl->i3sb, C * J * 4 * FSZ * b) && pl->alloc(&pl->gsum, C * 8 * FSZ * b) &&
+         pl->alloc(&pl->i3t, C * J * 4 * FSZ * b) && pl->alloc(&pl->lamh, C * 4 * FSZ * b) &&
          pl->alloc(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
          pl->alloc((void**)&pl->lflux, 2 * sizeof(double));
 }
@@ -418,6 +429,8 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.i3s = (T*)pl->i3s;
   d.i3o = (T*)pl->i3o;
   d.i3sum = (T*)pl->i3sum;
+  d.i3p = (T*)pl->i3p;
+  d.i3ps = (T*)pl->i3ps;
   d.lamP = (T*)pl->lamP;
   d.acot = (T*)pl->acot;
   d.gspec = (T*)pl->gspec;
@@ -426,6 +439,8 @@ DevPlan<T> devplan(qb_plan_s* pl) {
   d.i3g = (T*)pl->i3g;
   d.i3sb = (T*)pl->i3sb;
   d.gsum = (T*)pl->gsum;
+  d.i3t = (T*)pl->i3t;
+  d.lamh = (T*)pl->lamh;
   return d;
 }
 
