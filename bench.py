@@ -29,13 +29,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def i3_flops(ncells, N, J, M):
-    """Algorithmic flops of one I_3 launch: per (cell, j, m) 18 complex
-    2N x 2N transforms (2 packed shift transforms + 8 packed convolutions of
-    two transforms each), 5 n log2 n flops per transform of n = (2N)^2 points."""
-    P = 2 * N
-    n = P * P
-    return ncells * J * M * 18 * 5.0 * n * math.log2(n)
+def i3_transforms(J, M, paired):
+    """Complex P x P transforms of one I_3 evaluation per cell.  Unpaired:
+    per (j, m) 2 packed shift transforms + 8 packed convolutions of two
+    transforms = 18.  Paired Gauss-Legendre nodes (m, M-1-m): 2 shifts + 16
+    convolution transforms + 2 transforms of the partner sums = 20 per pair,
+    18 for the middle node of an odd M."""
+    if not paired:
+        return J * M * 18
+    return J * ((M // 2) * 20 + (M % 2) * 18)
+
+
+def i3_flops(ncells, N, J, M, paired):
+    """Flops of one I_3 launch at 5 n log2 n per complex transform of
+    n = (2N)^2 points, for the decomposition the kernel runs."""
+    n = (2 * N) ** 2
+    return ncells * i3_transforms(J, M, paired) * 5.0 * n * math.log2(n)
+
+
+def pairs_nodes(precision, tile):
+    """Whether the I_3 kernel pairs the Gauss-Legendre nodes (it does when
+    the partner sums, 2 E values per thread, fit in 64 registers)."""
+    return 2 * tile * (8 if precision == "f64" else 4) // 4 <= 64
 
 
 def run_gpu(wl, precision, steps, warmup):
@@ -46,6 +61,9 @@ def run_gpu(wl, precision, steps, warmup):
     prob = qb.Problem(wl.Nx, wl.N, wl.J, wl.M, wl.L, wl.R, precision,
                       qb.BC.from_workload(wl.left), qb.BC.from_workload(wl.right))
     plan = qb.Plan(prob)
+    plan.tune()
+    cfg = plan.config()
+    log(f"[{precision}] tuned tile E = {cfg['tile']}")
     W = torch.from_numpy(wl.W0).to(cdt).cuda().contiguous()
     B = torch.from_numpy(wl.B).cuda().contiguous()
     mom = torch.zeros((steps + 1, wl.Nx, 7), dtype=torch.float64, device="cuda")
@@ -67,7 +85,7 @@ def run_gpu(wl, precision, steps, warmup):
     m = mom.cpu().numpy()
     tot0, tot1 = m[0].sum(0), m[-1].sum(0)
     plan.close()
-    return t1 - t0, kern, tot0, tot1
+    return t1 - t0, kern, tot0, tot1, cfg
 
 
 def run_adjoint(steps, every):
@@ -84,6 +102,8 @@ def run_adjoint(steps, every):
     wl = workloads.config(5)
     plan = qb.Plan(qb.Problem(wl.Nx, wl.N, wl.J, wl.M, wl.L, wl.R, "f64"))
     plan.enable_adjoint()
+    plan.tune()
+    cfg = plan.config()
     W0 = torch.from_numpy(wl.W0).cuda().contiguous()
     B = torch.from_numpy(wl.B).cuda().contiguous()
     h2 = (2 * wl.L / wl.N) ** 2
@@ -102,21 +122,33 @@ def run_adjoint(steps, every):
     torch.cuda.synchronize()
     t_fwd = time.perf_counter() - t0
     log(f"[adjoint] forward {steps} steps {t_fwd:.3f} s")
-    Wr = W0.clone().requires_grad_(True)
-    Br = B.clone().requires_grad_(True)
-    t0 = time.perf_counter()
-    loss = loss_of(qb.evolve(plan, Wr, Br, wl.dt, steps, every))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    log(f"[adjoint] checkpointed forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+    def grad_run(k):
+        Wr = W0.clone().requires_grad_(True)
+        Br = B.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        loss = loss_of(qb.evolve(plan, Wr, Br, wl.dt, steps, k))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        log(f"[adjoint] checkpoint_every={k}: forward {t1 - t0:.3f} s, backward {t2 - t1:.3f} s")
+        return t1 - t0, t2 - t1, Wr.grad, Br.grad
+
+    f_ck, b_ck, gW, gB = grad_run(every)
+    f_all, b_all, gW2, gB2 = grad_run(0)
+    # the checkpoints pass through the complex layout, so the two modes agree
+    # to rounding, not bitwise
+    diff = max(float((gW - gW2).abs().max() / gW2.abs().max()), float((gB - gB2).abs().max() / gB2.abs().max()))
     plan.close()
     return {"workload": "adjoint_fd_periodic_B", "Nx": wl.Nx, "N": wl.N, "J": wl.J, "M": wl.M, "dtype": "f64",
-            "steps": steps, "checkpoint_every": every, "forward_s": t_fwd, "forward_with_checkpoints_s": t1 - t0,
-            "backward_s": t2 - t1, "ratio": (t2 - t1) / t_fwd,
-            "grad_norms": {"W0": float(Wr.grad.abs().max()), "B": float(Br.grad.abs().max())}}
+            "tile": cfg["tile"], "adjoint_variant": cfg["adjoint_variant"],
+            "steps": steps, "checkpoint_every": every, "forward_s": t_fwd,
+            "checkpointed": {"forward_s": f_ck, "backward_s": b_ck, "ratio": b_ck / t_fwd,
+                             "recomputed_steps": steps - min(every, steps - every * ((steps - 1) // every))},
+            "store_all": {"forward_s": f_all, "backward_s": b_all, "ratio": b_all / t_fwd},
+            "ratio": b_ck / t_fwd, "gradient_rel_diff_between_modes": diff,
+            "grad_norms": {"W0": float(gW.abs().max()), "B": float(gB.abs().max())}}
 
 
 def run_batch(steps, nprob):
@@ -207,7 +239,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the float64 run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--nx", type=int, default=None, help="fewer cells (profiling runs)")
-    ap.add_argument("--adj-steps", type=int, default=40,
+    ap.add_argument("--adj-steps", type=int, default=60,
                     help="steps of the adjoint/forward measurement (0 skips it)")
     ap.add_argument("--adj-every", type=int, default=20, help="checkpoint interval of the adjoint run")
     ap.add_argument("--batch-steps", type=int, default=1,
@@ -223,7 +255,7 @@ def main():
 
     wl = workloads.config(3, Nx=args.nx)
     log(f"workload {wl.name}: Nx={wl.Nx} N={wl.N} J={wl.J} M={wl.M} dt={wl.dt}")
-    t32, k32, a32, b32 = run_gpu(wl, "f32", args.steps, args.warmup)
+    t32, k32, a32, b32, cfg32 = run_gpu(wl, "f32", args.steps, args.warmup)
     out = {
         "metric": METRIC,
         "value": wl.Nx * args.steps / t32,
@@ -242,23 +274,26 @@ def main():
                    "moments": "f64"},
     }
 
-    def roof(kern, precision):
+    def roof(kern, precision, cfg):
         ms, n = kern["i3"]
         avg_s = ms / max(n, 1) / 1e3
-        ach = i3_flops(wl.Nx, wl.N, wl.J, wl.M) / avg_s / 1e12
+        paired = pairs_nodes(precision, cfg["tile"])
+        ach = i3_flops(wl.Nx, wl.N, wl.J, wl.M, paired) / avg_s / 1e12
         return {"kernel": "k_i3", "bound": "alu", "achieved": ach, "peak": PEAK[precision],
                 "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": None,
-                "avg_launch_ms": ms / max(n, 1), "launches": n}
+                "avg_launch_ms": ms / max(n, 1), "launches": n, "tile": cfg["tile"],
+                "paired_nodes": paired,
+                "transforms_per_cell": i3_transforms(wl.J, wl.M, paired)}
 
-    out["roofline"] = roof(k32, "f32")
+    out["roofline"] = roof(k32, "f32", cfg32)
     out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in k32.items()}
     drift = lambda a, b: {"density": float((b[0] - a[0]) / a[0]), "energy": float((b[6] - a[6]) / a[6])}
     out["moment_drift_f32"] = drift(a32, b32)
     if not args.no_f64:
-        t64, k64, a64, b64 = run_gpu(wl, "f64", args.steps, args.warmup)
+        t64, k64, a64, b64, cfg64 = run_gpu(wl, "f64", args.steps, args.warmup)
         out["value_f64"] = wl.Nx * args.steps / t64
         out["ms_per_step_f64"] = 1e3 * t64 / args.steps
-        out["roofline_f64"] = roof(k64, "f64")
+        out["roofline_f64"] = roof(k64, "f64", cfg64)
         out["moment_drift_f64"] = drift(a64, b64)
     out["adjoint_forward_ratio"] = None
     if args.adj_steps > 0:

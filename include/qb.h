@@ -140,7 +140,7 @@ qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream)
  * FFT tile shapes.  Every padded-grid transform runs in one workgroup that
  * holds the P x P field in registers, E elements per thread and P / E
  * threads per line.  Compiled shapes: P = 32: E = 16 (default), 8;
- * P = 64: E = 32 (default), 16; P = 128: E = 32.
+ * P = 64: E = 16 (default), 32; P = 128: E = 16 (default), 32.
  * ------------------------------------------------------------------------- */
 
 /* Use tile shape E on this plan (QB_ENOTSUP if not compiled for its P).
@@ -148,11 +148,20 @@ qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream)
 qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
 
 /* Autotuner: time the collision pipeline on the plan's first `ncells` cells
- * for every compiled tile shape and keep the fastest (synchronous; it
- * overwrites the plan's internal state buffer).  The choice is cached per
- * (precision, N, J, M, ncells) for the life of the process.  *tile (may be
- * NULL) receives the chosen E. */
+ * for every compiled tile shape and keep the fastest; when the plan's
+ * adjoint is enabled, also choose among the three I_3 adjoint kernels
+ * (accumulators in memory or in registers, see qb_plan_config).  Synchronous; overwrites the
+ * plan's internal buffers.  Choices are cached per (precision, N, J, M,
+ * ncells) for the life of the process.  *tile (may be NULL) receives E. */
 qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream);
+
+/* Use I_3 adjoint kernel `variant` (0, 1 or 2, see qb_plan_config). */
+qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant);
+
+/* Current tile shape E and I_3 adjoint kernel (0: accumulators in memory,
+ * 1: the shifted-field cotangent in registers, 2: also the w cotangent) of
+ * the plan; either pointer may be NULL. */
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent problems (uneven Nx and N) advanced together:

@@ -35,6 +35,8 @@ EXPORTS = (
     "qb_adjoint_step",
     "qb_plan_set_tile",
     "qb_plan_tune",
+    "qb_plan_config",
+    "qb_plan_set_adjoint_variant",
     "qb_batch_create",
     "qb_batch_destroy",
     "qb_batch_bytes",
@@ -124,6 +126,10 @@ def _declare(lib):
     lib.qb_plan_set_tile.restype = i32
     lib.qb_plan_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     lib.qb_plan_tune.restype = i32
+    lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qb_plan_config.restype = i32
+    lib.qb_plan_set_adjoint_variant.argtypes = [vp, i32]
+    lib.qb_plan_set_adjoint_variant.restype = i32
     lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
     lib.qb_batch_create.restype = i32
     lib.qb_batch_destroy.argtypes = [vp]
@@ -390,7 +396,7 @@ class Plan:
         return out
 
     # ------------------------------------------------------------ tiles
-    TILES = {32: (16, 8), 64: (32, 16), 128: (32,)}
+    TILES = {32: (16, 8), 64: (16, 32), 128: (16, 32)}
 
     def set_tile(self, E):
         """qb_plan_set_tile: FFT tile shape (elements per thread) of this plan."""
@@ -402,6 +408,16 @@ class Plan:
         n = self.problem.Nx if ncells is None else int(ncells)
         _check(self.lib.qb_plan_tune(self.handle, n, ctypes.byref(e), _stream()), "qb_plan_tune")
         return e.value
+
+    def set_adjoint_variant(self, v):
+        """qb_plan_set_adjoint_variant: I_3 adjoint kernel 0, 1 or 2."""
+        _check(self.lib.qb_plan_set_adjoint_variant(self.handle, int(v)), "qb_plan_set_adjoint_variant")
+
+    def config(self):
+        """qb_plan_config: (tile E, I_3 adjoint variant) currently in use."""
+        e, v = ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v)), "qb_plan_config")
+        return {"tile": e.value, "adjoint_variant": v.value}
 
     def profile(self, enable=True):
         """qb_profile: bracket every launch of this plan with HIP events."""

@@ -24,14 +24,45 @@ FLAGS = [
 ]
 
 
-def build(verbose=False, extra=None):
-    """Compile libqb.so; returns its path.  Raises CalledProcessError on failure."""
-    src = os.path.join(CSRC, "qb_lib.hip")
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC] + FLAGS + (extra or []) + [src, "-o", tmp]
+BUILD = os.path.join(HERE, "_build")
+
+
+def _units():
+    """qb_lib.hip (host code, ABI, small kernels) and the qb_tiles_*.hip
+    units (the FFT kernels of every tile shape), compiled separately."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith(".hip"))
+    return [os.path.join(CSRC, f) for f in names]
+
+
+def build(verbose=False, extra=None, jobs=None):
+    """Compile every unit to an object in parallel, then link libqb.so;
+    returns its path.  Raises CalledProcessError on failure."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    os.makedirs(BUILD, exist_ok=True)
+    units = _units()
+    objs = [os.path.join(BUILD, os.path.basename(u)[:-4] + ".o") for u in units]
+    compile_flags = [f for f in FLAGS if f != "-shared"]
+    cmds = [[HIPCC] + compile_flags + (extra or []) + ["-c", u, "-o", o] for u, o in zip(units, objs)]
     if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    jobs = jobs or min(len(cmds), max(1, os.cpu_count() or 1), 16)
+
+    def run(c):
+        return subprocess.run(c, capture_output=True, text=True)
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(run, cmds))
+    for c, r in zip(cmds, results):
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise subprocess.CalledProcessError(r.returncode, c)
+    tmp = LIB + ".tmp"
+    link = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + objs + ["-o", tmp]
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.run(link, check=True)
     os.replace(tmp, LIB)
     return LIB
 

@@ -533,6 +533,208 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp(DevPlan<T> d, in
   }
 }
 
+// Same transpose with the accumulators of each row pair held in registers:
+// for rows (a0, a1) the loop over nu runs the three convolutions q, u, r
+// back to back, so Y_a (from q and u) and, with WREG, w_bar_a (from r)
+// accumulate in registers; w_bar_nu and Y_nu go through memory once per
+// convolution.  The tuner picks between this kernel (with and without WREG)
+// and k_i3_vjp: the extra registers cost occupancy.
+template <typename T, int P, int E, bool WREG>
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d, int ncells) {
+  using K = Kern<T, P, E>;
+  constexpr unsigned S = sizeof(T);
+  __shared__ T smem[K::LDS];
+  Fft2<T, P, E> eng;
+  setup(eng, smem, d.tw);
+  const int task = xcd_task(blockIdx.x, gridDim.x);
+  const int cell = task / d.J;
+  const int j = task % d.J;
+  const unsigned vo = threadIdx.x * S;
+  const size_t tb = (size_t)cell * d.J + j;
+  const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
+  const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
+  const rsrc_t rl = mkbuf(d.acot + ((size_t)cell * 16 + 8) * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rh = mkbuf(d.lamh + (size_t)cell * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rg = mkbuf(d.i3g + tb * 8 * K::FSZ, 8 * K::FSZ);
+  const rsrc_t rb = mkbuf(d.i3s + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rt = mkbuf(d.i3t + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rc = mkbuf(d.i3sb + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
+  const int kx = eng.line;
+#pragma unroll 1
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int n = 0; n < E; ++n) bst<T>(rg, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+  auto conv = [&](T (&zr)[E], T (&zi)[E]) {
+    eng.fwd2(zr, zi);
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const T a = bld<T>(rm, vo, (k * K::NT) * S);
+      zr[k] *= a;
+      zi[k] *= a;
+    }
+    eng.inv2(zr, zi);
+  };
+  auto ld = [&](rsrc_t r, int plane, unsigned o) { return bld<T>(r, vo, (plane * K::FSZ + o) * S); };
+  auto rmw = [&](rsrc_t r, int plane, unsigned o, T v) {
+    const unsigned off = (plane * K::FSZ + o) * S;
+    bst<T>(r, bld<T>(r, vo, off) + v, vo, off);
+  };
+  const int nnode = (d.M + 1) / 2;
+#pragma unroll 1
+  for (int m = 0; m < nnode; ++m) {
+    const bool paired = m != d.M - 1 - m;
+    const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
+    const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
+    const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
+#pragma unroll 1
+    for (int src = 0; src < (paired ? 2 : 1); ++src) {
+#pragma unroll 1
+      for (int pr = 0; pr < 2; ++pr) {
+        T zr[E], zi[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const unsigned o = k * K::NT;
+          T er, ei;
+          cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
+          if (src == 0) {
+            const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
+            T ar, ai, br, bi;
+            cmul(bld<T>(rs, vo, (fa + o) * S), bld<T>(rs, vo, (fa + K::FSZ + o) * S), er, ei, ar, ai);
+            cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
+            zr[k] = ar - bi;
+            zi[k] = ai + br;
+          } else {
+            cmul(ld(rh, 2 * pr, o), ld(rh, 2 * pr + 1, o), er, ei, zr[k], zi[k]);
+          }
+        }
+        eng.inv2(zr, zi);
+        const T fa = src == 0 ? (T)1 : (T)(pr == 0 ? -2.0 * kPi : 2.0 * kPi);
+        const T fb = src == 0 ? (T)1 : (T)(2.0 * kPi);
+        const rsrc_t rd = src == 0 ? rb : rt;
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          bst<T>(rd, fa * zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
+          bst<T>(rd, fb * zi[n], vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
+        }
+      }
+    }
+    // Y (the S-transposed cotangent of this node pair) starts at zero
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int n = 0; n < E; ++n) bst<T>(rc, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+    const T c = d.wm[m];
+#pragma unroll 1
+    for (int mp = 0; mp < 2; ++mp) {
+      const int a0 = 2 * mp, a1 = 2 * mp + 1;
+      const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
+      T ya0[E], ya1[E], wa0[WREG ? E : 1], wa1[WREG ? E : 1];
+#pragma unroll
+      for (int n = 0; n < E; ++n) ya0[n] = ya1[n] = 0;
+      if constexpr (WREG) {
+#pragma unroll
+        for (int n = 0; n < E; ++n) wa0[WREG ? n : 0] = wa1[WREG ? n : 0] = 0;
+      }
+#pragma unroll 1
+      for (int nu = 0; nu < 4; ++nu) {
+        const T cnu = nu == 0 ? c : -c;
+        T zr[E], zi[E];
+        // q_a,nu = Psi(w_a s_nu)
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const unsigned o = n * K::NT;
+          const T sv = ld(rb, nu, o);
+          zr[n] = ld(rw, a0, o) * sv;
+          zi[n] = ld(rw, a1, o) * sv;
+        }
+        conv(zr, zi);
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const unsigned o = n * K::NT;
+          const T bb = ld(rl, nu, o);
+          ya0[n] += ca0 * bb * zr[n];
+          ya1[n] += ca1 * bb * zi[n];
+          if (paired) rmw(rg, nu, o, cnu * (ld(rt, a0, o) * zr[n] + ld(rt, a1, o) * zi[n]));
+        }
+        if (paired) {
+          // u_a,nu = Psi(t_nu w_a)
+#pragma unroll
+          for (int n = 0; n < E; ++n) {
+            const unsigned o = n * K::NT;
+            const T tv = ld(rt, nu, o);
+            zr[n] = tv * ld(rw, a0, o);
+            zi[n] = tv * ld(rw, a1, o);
+          }
+          conv(zr, zi);
+#pragma unroll
+          for (int n = 0; n < E; ++n) {
+            const unsigned o = n * K::NT;
+            const T wv = ld(rw, nu, o);
+            ya0[n] += ca0 * wv * zr[n];
+            ya1[n] += ca1 * wv * zi[n];
+            rmw(rg, nu, o, ca0 * ld(rb, a0, o) * zr[n] + ca1 * ld(rb, a1, o) * zi[n]);
+          }
+        }
+        // r_a,nu = Psi(b_bar_nu s_a)
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const unsigned o = n * K::NT;
+          const T bb = ld(rl, nu, o);
+          zr[n] = bb * ld(rb, a0, o);
+          zi[n] = bb * ld(rb, a1, o);
+        }
+        conv(zr, zi);
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const unsigned o = n * K::NT;
+          const T sv = ld(rb, nu, o);
+          if constexpr (WREG) {
+            wa0[WREG ? n : 0] += ca0 * sv * zr[n];
+            wa1[WREG ? n : 0] += ca1 * sv * zi[n];
+          } else {
+            rmw(rg, a0, o, ca0 * sv * zr[n]);
+            rmw(rg, a1, o, ca1 * sv * zi[n]);
+          }
+          rmw(rc, nu, o, ca0 * ld(rw, a0, o) * zr[n] + ca1 * ld(rw, a1, o) * zi[n]);
+        }
+      }
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const unsigned o = n * K::NT;
+        rmw(rc, a0, o, ya0[n]);
+        rmw(rc, a1, o, ya1[n]);
+        if constexpr (WREG) {
+          rmw(rg, a0, o, wa0[WREG ? n : 0]);
+          rmw(rg, a1, o, wa1[WREG ? n : 0]);
+        }
+      }
+    }
+    // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3)
+#pragma unroll 1
+    for (int pr = 0; pr < 2; ++pr) {
+      T zr[E], zi[E];
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const unsigned o = n * K::NT;
+        zr[n] = ld(rc, 2 * pr, o);
+        zi[n] = -ld(rc, 2 * pr + 1, o);
+      }
+      eng.fwd2(zr, zi);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const unsigned o = k * K::NT;
+        T er, ei;
+        cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
+        T xr, xi;
+        cmul(zr[k], -zi[k], er, ei, xr, xi);
+        rmw(rg, 4 + 2 * pr, o, xr);
+        rmw(rg, 5 + 2 * pr, o, xi);
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ gradient on the grid
 // Elementwise gathering of every cotangent of the interpolants and of
 // w_hat into gsum[cell][8] (flat index e, the same in both layouts):

@@ -221,7 +221,7 @@ struct Fft2 {
   static constexpr int ROUNDS = (P * LD * (int)sizeof(T) > QB_XPOSE_SPLIT_BYTES && P / 2 >= E) ? 2 : 1;
   static constexpr int RP = P / ROUNDS;
   static constexpr int LDS_SCALARS = RP * LD;
-  static_assert(TPR >= 1 && TPR <= 4 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2 or 4");
+  static_assert(TPR >= 1 && TPR <= 8 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2, 4 or 8");
   static_assert(E * TPR == P, "E * TPR must equal P");
   static_assert(P % BW == 0, "P must be a multiple of the bank width");
 
@@ -265,15 +265,38 @@ struct Fft2 {
     }
   }
 
+  // twiddle w_8^r, r = 0..3, of the H = 4 lane stage (conjugated for the
+  // inverse), as (re, im)
+  template <int SG>
+  __device__ __forceinline__ void w8(int r, T& wr, T& wi) const {
+    const T c = (T)0.70710678118654752440;
+    wr = r == 0 ? (T)1 : (r == 1 ? c : (r == 2 ? (T)0 : -c));
+    const T s = r == 0 ? (T)0 : (r == 2 ? (T)1 : c);
+    wi = SG < 0 ? -s : s;
+  }
+
   // Cross-lane DFT of size TPR for every k.  Forward (decimation in
   // frequency, natural lane order in, bit-reversed out):
   //   stage H = TPR/2 .. 1: lower lane z + o, upper lane (o - z) w_{2H}^{q mod H}
-  // For TPR <= 4 the only non-trivial stage twiddle is w_4 = -i (lane 3 of
-  // the H = 2 stage), applied as a component swap.
+  // The H = 2 stage twiddle is w_4 = -i (lanes with q mod 4 = 3), applied as a
+  // component swap; the H = 4 stage (TPR = 8) multiplies the upper lanes by
+  // w_8^{q mod 4}.
   __device__ __forceinline__ void lanes_fwd(T (&zr)[E], T (&zi)[E]) const {
-    if constexpr (TPR == 4) {
+    if constexpr (TPR == 8) {
+      const T sg = (q & 4) ? (T)-1 : (T)1;
+      T wr, wi;
+      w8<-1>((q & 4) ? (q & 3) : 0, wr, wi);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T orr = xor_lane<4>(zr[k]), oi = xor_lane<4>(zi[k]);
+        const T dr = sg * zr[k] + orr, di = sg * zi[k] + oi;
+        zr[k] = dr * wr - di * wi;
+        zi[k] = dr * wi + di * wr;
+      }
+    }
+    if constexpr (TPR >= 4) {
       const T sg = (q & 2) ? (T)-1 : (T)1;
-      const bool rot = q == 3;
+      const bool rot = (q & 3) == 3;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const T orr = xor_lane<2>(zr[k]), oi = xor_lane<2>(zi[k]);
@@ -303,15 +326,27 @@ struct Fft2 {
         zi[k] = sg * zi[k] + oi;
       }
     }
-    if constexpr (TPR == 4) {
+    if constexpr (TPR >= 4) {
       const T sg = (q & 2) ? (T)-1 : (T)1;
-      const bool rot = q == 3;
+      const bool rot = (q & 3) == 3;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        // undo the -i of lane 3: multiply by +i = (-z_i, z_r)
+        // undo the -i of lanes q mod 4 = 3: multiply by +i = (-z_i, z_r)
         const T ar = rot ? -zi[k] : zr[k];
         const T ai = rot ? zr[k] : zi[k];
         const T orr = xor_lane<2>(ar), oi = xor_lane<2>(ai);
+        zr[k] = sg * ar + orr;
+        zi[k] = sg * ai + oi;
+      }
+    }
+    if constexpr (TPR == 8) {
+      const T sg = (q & 4) ? (T)-1 : (T)1;
+      T wr, wi;
+      w8<+1>((q & 4) ? (q & 3) : 0, wr, wi);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const T ar = zr[k] * wr - zi[k] * wi, ai = zr[k] * wi + zi[k] * wr;
+        const T orr = xor_lane<4>(ar), oi = xor_lane<4>(ai);
         zr[k] = sg * ar + orr;
         zi[k] = sg * ai + oi;
       }

@@ -21,15 +21,15 @@ struct Cfg;
 template <>
 struct Cfg<double, 32> { static constexpr int E = 16; };
 template <>
-struct Cfg<double, 64> { static constexpr int E = 32; };
+struct Cfg<double, 64> { static constexpr int E = 16; };
 template <>
-struct Cfg<double, 128> { static constexpr int E = 32; };
+struct Cfg<double, 128> { static constexpr int E = 16; };
 template <>
 struct Cfg<float, 32> { static constexpr int E = 16; };
 template <>
-struct Cfg<float, 64> { static constexpr int E = 32; };
+struct Cfg<float, 64> { static constexpr int E = 16; };
 template <>
-struct Cfg<float, 128> { static constexpr int E = 32; };
+struct Cfg<float, 128> { static constexpr int E = 16; };
 
 // Device-side view of the plan's tables and buffers (all device pointers).
 template <typename T>
@@ -769,13 +769,13 @@ __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T
 
 // ------------------------------------------------------------------ batch helpers
 // dst[0..n) = src[0..n), or zeros for a NULL source (a problem without field)
-__global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int n) {
+static __global__ void k_copy_f64(const double* __restrict__ src, double* __restrict__ dst, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src ? src[i] : 0.0;
 }
 
 // one problem's moments [snap][Nx][7] out of the batch moments [snap][Ntot][7]
-__global__ void k_scatter_moments(const double* __restrict__ src, double* __restrict__ dst, int nsnap, int Ntot,
+static __global__ void k_scatter_moments(const double* __restrict__ src, double* __restrict__ dst, int nsnap, int Ntot,
                                   int off, int Nx) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = Nx * 7;

@@ -1,5 +1,7 @@
 // Host side of the solver: plan creation (quadrature tables of Sec. 3.2,
-// device buffers), kernel launch sequences and the C ABI declared in qb.h.
+// device buffers), launch sequences of the step, batches, tuning and the C
+// ABI declared in qb.h.  The collision pipelines (the FFT kernels of every
+// tile shape) are compiled in the qb_tiles_*.hip units.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -11,21 +13,19 @@
 #include <string>
 #include <vector>
 
-#include "qb.h"
-#include "qb_adjoint.hpp"
-#include "qb_kernels.hpp"
-
-using qb::DevPlan;
+#include "qb_plan.hpp"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
 bool hip_ok(hipError_t e, const char* what) {
   if (e == hipSuccess) return true;
   g_last_error = std::string(what) + ": " + hipGetErrorString(e);
   return false;
 }
+
+namespace {
 
 // ------------------------------------------------------------------ quadrature (host, float64)
 // phi_R(x) = int_0^R sin(pi x r / L) dr = (2L/(pi x)) sin^2(pi R x / (2L)), phi_R(0) = 0
@@ -85,79 +85,6 @@ int cfg_E(int precision, int P) {
 }
 
 }  // namespace
-
-struct qb_plan_s {
-  qb_problem prob;
-  int P, E, NT, TPR;
-  int wcells;  // cells per collision launch (the workspace holds this many)
-  size_t bytes = 0;
-  std::vector<void*> allocs;
-  // quadrature tables in the FFT engine's element order, one set per tile
-  // shape E (elements per thread) that has been selected on this plan
-  struct TabSet {
-    int E = 0;
-    void *tw = nullptr, *phip = nullptr, *Kt = nullptr, *psi = nullptr, *psip = nullptr, *psiw = nullptr,
-         *psips = nullptr;
-  };
-  std::vector<TabSet> tabs;
-  int cur_tab = 0;
-  void *phx, *phy, *wm;  // natural order, independent of the tile
-  void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum, *i3p, *i3ps;
-  void *st0, *st1, *st2, *cbuf, *bcw;
-  double* flux;
-  // adjoint workspace (qb_plan_enable_adjoint)
-  bool adjoint = false;
-  void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
-       *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
-  void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
-       *cg = nullptr, *g0 = nullptr, *ext = nullptr;
-  double* lflux = nullptr;
-  qb::BcDev bl, br;
-  // kernel timing
-  bool profiling = false;
-  struct Rec {
-    int kernel;
-    hipEvent_t a, b;
-  };
-  std::vector<Rec> recs;
-  std::vector<hipEvent_t> pool;
-
-  bool alloc(void** p, size_t n) {
-    if (!hip_ok(hipMalloc(p, n), "hipMalloc")) return false;
-    allocs.push_back(*p);
-    bytes += n;
-    return true;
-  }
-  ~qb_plan_s() {
-    for (auto& r : recs) {
-      (void)hipEventDestroy(r.a);
-      (void)hipEventDestroy(r.b);
-    }
-    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
-  }
-  hipEvent_t event() {
-    if (!pool.empty()) {
-      hipEvent_t e = pool.back();
-      pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
-  }
-  // bracket one launch: call begin() before and end() after the launch
-  int begin(int kernel, hipStream_t s) {
-    if (!profiling) return -1;
-    Rec r{kernel, event(), event()};
-    (void)hipEventRecord(r.a, s);
-    recs.push_back(r);
-    return (int)recs.size() - 1;
-  }
-  void end(int id, hipStream_t s) {
-    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
-  }
-};
 
 namespace {
 
@@ -402,81 +329,14 @@ bool build_adjoint(qb_plan_s* pl) {
          pl->alloc((void**)&pl->lflux, 2 * sizeof(double));
 }
 
-template <typename T>
-DevPlan<T> devplan(qb_plan_s* pl) {
-  DevPlan<T> d;
-  d.Nx = pl->prob.Nx;
-  d.N = pl->prob.N;
-  d.J = pl->prob.J;
-  d.M = pl->prob.M;
-  d.P = pl->P;
-  d.L = (T)pl->prob.L;
-  const qb_plan_s::TabSet& ts = pl->tabs[pl->cur_tab];
-  d.tw = (const T*)ts.tw;
-  d.phip = (const T*)ts.phip;
-  d.Kt = (const T*)ts.Kt;
-  d.psi = (const T*)ts.psi;
-  d.psip = (const T*)ts.psip;
-  d.psiw = (const T*)ts.psiw;
-  d.psips = (const T*)ts.psips;
-  d.phx = (const T*)pl->phx;
-  d.phy = (const T*)pl->phy;
-  d.wm = (const T*)pl->wm;
-  d.spec = (T*)pl->spec;
-  d.wP = (T*)pl->wP;
-  d.terms = (T*)pl->terms;
-  d.acc = (T*)pl->acc;
-  d.i3s = (T*)pl->i3s;
-  d.i3o = (T*)pl->i3o;
-  d.i3sum = (T*)pl->i3sum;
-  d.i3p = (T*)pl->i3p;
-  d.i3ps = (T*)pl->i3ps;
-  d.lamP = (T*)pl->lamP;
-  d.acot = (T*)pl->acot;
-  d.gspec = (T*)pl->gspec;
-  d.gf0 = (T*)pl->gf0;
-  d.tsb = (T*)pl->tsb;
-  d.i3g = (T*)pl->i3g;
-  d.i3sb = (T*)pl->i3sb;
-  d.gsum = (T*)pl->gsum;
-  d.i3t = (T*)pl->i3t;
-  d.lamh = (T*)pl->lamh;
-  return d;
-}
-
-int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
-
-// C[w] for cells [0, ncells) of the Pauli state w -> c (both [4][Nx][N][N])
-// C[w] for the cells [cell0, cell0 + ncells) of the state arrays w, c
-// (ncells <= wcells; the workspace holds the chunk's cells from index 0)
-template <typename T, int P, int E>
-bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s) {
-  constexpr int NT = qb::Fft2<T, P, E>::NT;
-  DevPlan<T> d = devplan<T>(pl);
-  int id = pl->begin(QB_K_DFT_IN, s);
-  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
-  pl->end(id, s);
-  id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
-  pl->end(id, s);
-  id = pl->begin(QB_K_I3, s);
-  hipLaunchKernelGGL((qb::k_i3<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
-  pl->end(id, s);
-  const size_t nel = (size_t)ncells * P * P;
-  hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
-  id = pl->begin(QB_K_COMBINE, s);
-  hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, cell0);
-  pl->end(id, s);
-  return hip_ok(hipGetLastError(), "collision launch");
-}
 
 // Tile shapes (elements per thread E; lanes per line P / E) compiled for
 // each padded grid size; the first is the default, qb_plan_tune picks one.
 std::vector<int> tile_candidates(int P) {
   switch (P) {
     case 32: return {16, 8};
-    case 64: return {32, 16};
-    default: return {32};
+    case 64: return {16, 32};
+    default: return {16, 32};
   }
 }
 
@@ -489,7 +349,9 @@ bool collision_chunk(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hip
     case 64:
       return pl->E == 16 ? collision_pipeline<T, 64, 16>(pl, w, c, ncells, cell0, s)
                          : collision_pipeline<T, 64, 32>(pl, w, c, ncells, cell0, s);
-    case 128: return collision_pipeline<T, 128, 32>(pl, w, c, ncells, cell0, s);
+    case 128:
+      return pl->E == 16 ? collision_pipeline<T, 128, 16>(pl, w, c, ncells, cell0, s)
+                         : collision_pipeline<T, 128, 32>(pl, w, c, ncells, cell0, s);
   }
   return false;
 }
@@ -548,34 +410,6 @@ bool transport_to(qb_plan_s* pl, const T* src, T* dst, double dt, hipStream_t s)
 }
 
 // ------------------------------------------------------------------ adjoint pipelines
-// out = C'(w)^T lam for cells [0, ncells) (Pauli state layout, gradients)
-template <typename T, int P, int E>
-bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, int cell0,
-                            hipStream_t s) {
-  constexpr int NT = qb::Fft2<T, P, E>::NT;
-  DevPlan<T> d = devplan<T>(pl);
-  int id = pl->begin(QB_K_DFT_IN, s);
-  hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
-  pl->end(id, s);
-  id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
-  pl->end(id, s);
-  id = pl->begin(QB_K_ADJOINT, s);
-  hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, cell0);
-  const size_t nel = (size_t)ncells * P * P;
-  hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
-  hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
-  pl->end(id, s);
-  id = pl->begin(QB_K_I3_ADJOINT, s);
-  hipLaunchKernelGGL((qb::k_i3_vjp<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
-  pl->end(id, s);
-  id = pl->begin(QB_K_ADJOINT, s);
-  hipLaunchKernelGGL((qb::k_grad_pre<T>), dim3(blocks(nel * 8, 256)), dim3(256), 0, s, d, ncells, P * P);
-  hipLaunchKernelGGL((qb::k_grad_out<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, out, cell0);
-  pl->end(id, s);
-  return hip_ok(hipGetLastError(), "collision adjoint launch");
-}
-
 template <typename T>
 bool collision_vjp_chunk(qb_plan_s* pl, const T* w, const T* lam, T* out, int n, int c0, hipStream_t s) {
   switch (pl->P) {
@@ -585,7 +419,9 @@ bool collision_vjp_chunk(qb_plan_s* pl, const T* w, const T* lam, T* out, int n,
     case 64:
       return pl->E == 16 ? collision_vjp_pipeline<T, 64, 16>(pl, w, lam, out, n, c0, s)
                          : collision_vjp_pipeline<T, 64, 32>(pl, w, lam, out, n, c0, s);
-    case 128: return collision_vjp_pipeline<T, 128, 32>(pl, w, lam, out, n, c0, s);
+    case 128:
+      return pl->E == 16 ? collision_vjp_pipeline<T, 128, 16>(pl, w, lam, out, n, c0, s)
+                         : collision_vjp_pipeline<T, 128, 32>(pl, w, lam, out, n, c0, s);
   }
   return false;
 }
@@ -860,6 +696,39 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
   }
   if (!select_tile<T>(pl, best)) return QB_EHIP;
   if (chosen) *chosen = best;
+  if (pl->adjoint) {
+    // the two I_3 adjoint kernels (memory or register accumulators)
+    const TuneKey vkey{p.precision + 16, p.N, p.J, p.M, ncells * 1000 + best};
+    auto vt = tune_cache().find(vkey);
+    if (vt != tune_cache().end()) {
+      pl->vjp_variant = vt->second;
+    } else {
+      T* w = (T*)pl->st0;
+      T* g = (T*)pl->g0;
+      T* out = (T*)pl->cg;
+      const size_t n = (size_t)4 * p.Nx * p.N * p.N * sizeof(T);
+      if (!hip_ok(hipMemsetAsync(w, 0, n, s), "hipMemsetAsync") || !hip_ok(hipMemsetAsync(g, 0, n, s), "hipMemsetAsync"))
+        return QB_EHIP;
+      const bool prof = pl->profiling;
+      pl->profiling = false;
+      hipEvent_t a = pl->event(), b = pl->event();
+      float t[3] = {0.f, 0.f, 0.f};
+      for (int v = 0; v < 3; ++v) {
+        pl->vjp_variant = v;
+        if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
+        (void)hipEventRecord(a, s);
+        if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
+        (void)hipEventRecord(b, s);
+        if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
+        (void)hipEventElapsedTime(&t[v], a, b);
+      }
+      pl->pool.push_back(a);
+      pl->pool.push_back(b);
+      pl->profiling = prof;
+      pl->vjp_variant = (int)(std::min_element(t, t + 3) - t);
+      tune_cache()[vkey] = pl->vjp_variant;
+    }
+  }
   return QB_OK;
 }
 
@@ -1205,6 +1074,19 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E) {
   if (std::find(c.begin(), c.end(), (int)E) == c.end()) return QB_ENOTSUP;
   const bool ok = plan->prob.precision == QB_F64 ? select_tile<double>(plan, E) : select_tile<float>(plan, E);
   return ok ? QB_OK : QB_EHIP;
+}
+
+qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant) {
+  if (!plan || variant < 0 || variant > 2) return QB_EINVAL;
+  plan->vjp_variant = variant;
+  return QB_OK;
+}
+
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant) {
+  if (!plan) return QB_EINVAL;
+  if (tile) *tile = plan->E;
+  if (adjoint_variant) *adjoint_variant = plan->vjp_variant;
+  return QB_OK;
 }
 
 qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream) {

@@ -1,0 +1,148 @@
+// Internal host interface shared by qb_lib.hip and the per-tile
+// compilation units: the plan object, launch helpers and the collision
+// pipelines (forward and reverse) instantiated for every tile shape.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "qb.h"
+#include "qb_adjoint.hpp"
+#include "qb_kernels.hpp"
+
+using qb::DevPlan;
+
+// Records the text of a failed HIP call for qb_last_error(); true on success.
+bool hip_ok(hipError_t e, const char* what);
+
+inline int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
+
+struct qb_plan_s {
+  qb_problem prob;
+  int P, E, NT, TPR;
+  int wcells;  // cells per collision launch (the workspace holds this many)
+  int vjp_variant = 0;  // I_3 adjoint: 0 accumulators in memory, 1 Y in registers, 2 Y and w_bar (tuned)
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  // quadrature tables in the FFT engine's element order, one set per tile
+  // shape E (elements per thread) that has been selected on this plan
+  struct TabSet {
+    int E = 0;
+    void *tw = nullptr, *phip = nullptr, *Kt = nullptr, *psi = nullptr, *psip = nullptr, *psiw = nullptr,
+         *psips = nullptr;
+  };
+  std::vector<TabSet> tabs;
+  int cur_tab = 0;
+  void *phx, *phy, *wm;  // natural order, independent of the tile
+  void *spec, *wP, *terms, *acc, *i3s = nullptr, *i3o, *i3sum, *i3p, *i3ps;
+  void *st0, *st1, *st2, *cbuf, *bcw;
+  double* flux;
+  // adjoint workspace (qb_plan_enable_adjoint)
+  bool adjoint = false;
+  void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
+       *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
+  void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
+       *cg = nullptr, *g0 = nullptr, *ext = nullptr;
+  double* lflux = nullptr;
+  qb::BcDev bl, br;
+  // kernel timing
+  bool profiling = false;
+  struct Rec {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+
+  bool alloc(void** p, size_t n) {
+    if (!hip_ok(hipMalloc(p, n), "hipMalloc")) return false;
+    allocs.push_back(*p);
+    bytes += n;
+    return true;
+  }
+  ~qb_plan_s() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  hipEvent_t event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  // bracket one launch: call begin() before and end() after the launch
+  int begin(int kernel, hipStream_t s) {
+    if (!profiling) return -1;
+    Rec r{kernel, event(), event()};
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int id, hipStream_t s) {
+    if (id >= 0) (void)hipEventRecord(recs[id].b, s);
+  }
+};
+
+
+template <typename T>
+inline DevPlan<T> devplan(qb_plan_s* pl) {
+  DevPlan<T> d;
+  d.Nx = pl->prob.Nx;
+  d.N = pl->prob.N;
+  d.J = pl->prob.J;
+  d.M = pl->prob.M;
+  d.P = pl->P;
+  d.L = (T)pl->prob.L;
+  const qb_plan_s::TabSet& ts = pl->tabs[pl->cur_tab];
+  d.tw = (const T*)ts.tw;
+  d.phip = (const T*)ts.phip;
+  d.Kt = (const T*)ts.Kt;
+  d.psi = (const T*)ts.psi;
+  d.psip = (const T*)ts.psip;
+  d.psiw = (const T*)ts.psiw;
+  d.psips = (const T*)ts.psips;
+  d.phx = (const T*)pl->phx;
+  d.phy = (const T*)pl->phy;
+  d.wm = (const T*)pl->wm;
+  d.spec = (T*)pl->spec;
+  d.wP = (T*)pl->wP;
+  d.terms = (T*)pl->terms;
+  d.acc = (T*)pl->acc;
+  d.i3s = (T*)pl->i3s;
+  d.i3o = (T*)pl->i3o;
+  d.i3sum = (T*)pl->i3sum;
+  d.i3p = (T*)pl->i3p;
+  d.i3ps = (T*)pl->i3ps;
+  d.lamP = (T*)pl->lamP;
+  d.acot = (T*)pl->acot;
+  d.gspec = (T*)pl->gspec;
+  d.gf0 = (T*)pl->gf0;
+  d.tsb = (T*)pl->tsb;
+  d.i3g = (T*)pl->i3g;
+  d.i3sb = (T*)pl->i3sb;
+  d.gsum = (T*)pl->gsum;
+  d.i3t = (T*)pl->i3t;
+  d.lamh = (T*)pl->lamh;
+  return d;
+}
+
+
+// C[w] for the cells [cell0, cell0 + ncells) of the Pauli state arrays w, c
+// ([4][Nx][N][N]); ncells <= wcells, the workspace holds the chunk's cells
+// from index 0.  Defined in qb_pipelines.hpp.
+template <typename T, int P, int E>
+bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s);
+
+// out = C'(w)^T lam for the same cells (Pauli gradients).
+template <typename T, int P, int E>
+bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, int cell0,
+                            hipStream_t s);

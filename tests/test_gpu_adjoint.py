@@ -79,6 +79,28 @@ def test_collision_vjp_matches_oracle(precision, N, J, M, ncells):
     plan.close()
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("N,E,M", [(16, 8, 5), (32, 16, 4), (64, 32, 3), (64, 16, 4)])
+def test_collision_vjp_every_kernel_variant(precision, N, E, M, variant):
+    """Every I_3 adjoint kernel (accumulators in memory / registers) on
+    every tile shape family, odd and even M, against the oracle."""
+    import torch
+    rng = np.random.default_rng(7 * N + M)
+    w = wl.config(3, Nx=2, N=N)
+    plan = make_plan(w, precision, 4, M)
+    plan.set_tile(E)
+    plan.set_adjoint_variant(variant)
+    lam = rng.standard_normal((2, N, N, 4))
+    G = plan.collision_vjp(to_dev(w.W0, precision), to_dev(cot_api(lam), precision))
+    torch.cuda.synchronize()
+    t = oc.Tables(N, w.L, w.R, 4, M)
+    s = pauli.to_pauli(w.W0)
+    ref = np.stack([oad.collision_pauli_vjp(s[c], lam[c], w.L, w.R, 4, M, t) for c in range(2)])
+    assert rel(cot_pauli(G), ref) < TOL[precision]
+    plan.close()
+
+
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("cfg", [2, 3])
 def test_transport_vjp_matches_oracle(cfg, precision):
@@ -142,11 +164,13 @@ def test_step_trace_matches_step():
     plan.close()
 
 
-def test_evolve_gradient_matches_oracle_reduced_configuration5():
+@pytest.mark.parametrize("every", [6, 0])
+def test_evolve_gradient_matches_oracle_reduced_configuration5(every):
     """Gradient of dx h^2 sum g(x_j) tr(sigma_z W(T)) after 20 steps
     (configuration-5 recipe, Nx = 8, N = 16, J = M = 8) in the initial state
     and the field, through torch autograd with checkpoints every 6 steps
-    (segments 6, 6, 6, 2), against the stored oracle gradient."""
+    (segments 6, 6, 6, 2) and with every step's record kept, against the
+    stored oracle gradient."""
     import torch
     import paper_1408_1782_amd as qb
     p = os.path.join(GOLDEN, "c5_reduced_grad.npz")
@@ -157,7 +181,7 @@ def test_evolve_gradient_matches_oracle_reduced_configuration5():
     plan = make_plan(w, "f64", 8, 8)
     W0 = to_dev(w.W0, "f64").requires_grad_(True)
     B = torch.from_numpy(w.B).cuda().contiguous().requires_grad_(True)
-    WT = qb.evolve(plan, W0, B, w.dt, 20, checkpoint_every=6)
+    WT = qb.evolve(plan, W0, B, w.dt, 20, checkpoint_every=every)
     h2 = (2 * w.L / w.N) ** 2
     wt = torch.from_numpy(g["weight"]).cuda()
     # tr(sigma_z W) = W_00 - W_11

@@ -43,7 +43,7 @@ def problem(w, precision, J, M, Nx=None):
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("N,E", [(16, 16), (16, 8), (32, 32), (32, 16), (64, 32)])
+@pytest.mark.parametrize("N,E", [(16, 16), (16, 8), (32, 32), (32, 16), (64, 32), (64, 16)])
 def test_every_tile_matches_oracle(precision, N, E):
     import torch
     import paper_1408_1782_amd as qb
