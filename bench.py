@@ -29,6 +29,47 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC = os.path.join(HERE, "profiles", "k_i3_slab_N64_traffic.json")
+KERNEL_SOURCES = ("qb_fft.hpp", "qb_kernels.hpp", "qb_pipelines.hpp")
+
+
+def kernel_source_hash():
+    """sha256 over the sources of the forward collision kernels."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1408_1782_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision, tile):
+    """HBM bytes per k_i3 launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by a copy kernel of known size), or None when
+    they were taken on other kernel sources or another configuration."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ok = (t.get("source_sha256") == kernel_source_hash() and t.get("precision") == precision
+          and t.get("tile") == tile)
+    return t.get("bytes_per_launch") if ok else None
+
+
+def copy_calibration(mib=512):
+    """One device-to-device copy of `mib` MiB (a kernel of known traffic:
+    reads and writes mib MiB), for scaling the HBM byte counters."""
+    import torch
+
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {mib} MiB read, {mib} MiB written")
+
+
 def i3_transforms(J, M, paired):
     """Complex P x P transforms of one I_3 evaluation per cell.  Unpaired:
     per (j, m) 2 packed shift transforms + 8 packed convolutions of two
@@ -46,11 +87,6 @@ def i3_flops(ncells, N, J, M, paired):
     n = (2 * N) ** 2
     return ncells * i3_transforms(J, M, paired) * 5.0 * n * math.log2(n)
 
-
-def pairs_nodes(precision, tile):
-    """Whether the I_3 kernel pairs the Gauss-Legendre nodes (it does when
-    the partner sums, 2 E values per thread, fit in 64 registers)."""
-    return 2 * tile * (8 if precision == "f64" else 4) // 4 <= 64
 
 
 def run_gpu(wl, precision, steps, warmup):
@@ -245,6 +281,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="steps of the uneven-batch measurement (0 skips it)")
     ap.add_argument("--batch-problems", type=int, default=64, help="problems in the uneven batch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 512 MiB device copy first (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -253,6 +291,8 @@ def main():
 
     import workloads
 
+    if args.calibrate_copy:
+        copy_calibration()
     wl = workloads.config(3, Nx=args.nx)
     log(f"workload {wl.name}: Nx={wl.Nx} N={wl.N} J={wl.J} M={wl.M} dt={wl.dt}")
     t32, k32, a32, b32, cfg32 = run_gpu(wl, "f32", args.steps, args.warmup)
@@ -277,10 +317,11 @@ def main():
     def roof(kern, precision, cfg):
         ms, n = kern["i3"]
         avg_s = ms / max(n, 1) / 1e3
-        paired = pairs_nodes(precision, cfg["tile"])
+        paired = cfg["paired_nodes"]
         ach = i3_flops(wl.Nx, wl.N, wl.J, wl.M, paired) / avg_s / 1e12
+        traffic = measured_traffic(precision, cfg["tile"]) if wl.Nx == 256 else None
         return {"kernel": "k_i3", "bound": "alu", "achieved": ach, "peak": PEAK[precision],
-                "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": traffic,
                 "avg_launch_ms": ms / max(n, 1), "launches": n, "tile": cfg["tile"],
                 "paired_nodes": paired,
                 "transforms_per_cell": i3_transforms(wl.J, wl.M, paired)}

@@ -148,20 +148,26 @@ qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream)
 qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
 
 /* Autotuner: time the collision pipeline on the plan's first `ncells` cells
- * for every compiled tile shape and keep the fastest; when the plan's
+ * for every compiled tile shape, with and without Gauss-Legendre node
+ * pairing in the I_3 kernel, and keep the fastest; when the plan's
  * adjoint is enabled, also choose among the three I_3 adjoint kernels
  * (accumulators in memory or in registers, see qb_plan_config).  Synchronous; overwrites the
  * plan's internal buffers.  Choices are cached per (precision, N, J, M,
  * ncells) for the life of the process.  *tile (may be NULL) receives E. */
 qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream);
 
+/* I_3 kernel with (1) or without (0) Gauss-Legendre node pairing; both
+ * compute the same operator (the pairing uses rho_{M-1-m} = -rho_m). */
+qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired);
+
 /* Use I_3 adjoint kernel `variant` (0, 1 or 2, see qb_plan_config). */
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant);
 
-/* Current tile shape E and I_3 adjoint kernel (0: accumulators in memory,
- * 1: the shifted-field cotangent in registers, 2: also the w cotangent) of
- * the plan; either pointer may be NULL. */
-qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant);
+/* Current tile shape E, I_3 adjoint kernel (0: accumulators in memory,
+ * 1: the shifted-field cotangent in registers, 2: also the w cotangent) and
+ * whether the I_3 kernel of this tile pairs the Gauss-Legendre nodes m and
+ * M-1-m (1) or runs every node on its own (0); any pointer may be NULL. */
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent problems (uneven Nx and N) advanced together:

@@ -37,6 +37,7 @@ EXPORTS = (
     "qb_plan_tune",
     "qb_plan_config",
     "qb_plan_set_adjoint_variant",
+    "qb_plan_set_pairing",
     "qb_batch_create",
     "qb_batch_destroy",
     "qb_batch_bytes",
@@ -126,10 +127,12 @@ def _declare(lib):
     lib.qb_plan_set_tile.restype = i32
     lib.qb_plan_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     lib.qb_plan_tune.restype = i32
-    lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.qb_plan_config.restype = i32
     lib.qb_plan_set_adjoint_variant.argtypes = [vp, i32]
     lib.qb_plan_set_adjoint_variant.restype = i32
+    lib.qb_plan_set_pairing.argtypes = [vp, i32]
+    lib.qb_plan_set_pairing.restype = i32
     lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
     lib.qb_batch_create.restype = i32
     lib.qb_batch_destroy.argtypes = [vp]
@@ -413,11 +416,16 @@ class Plan:
         """qb_plan_set_adjoint_variant: I_3 adjoint kernel 0, 1 or 2."""
         _check(self.lib.qb_plan_set_adjoint_variant(self.handle, int(v)), "qb_plan_set_adjoint_variant")
 
+    def set_pairing(self, paired):
+        """qb_plan_set_pairing: I_3 kernel with or without node pairing."""
+        _check(self.lib.qb_plan_set_pairing(self.handle, 1 if paired else 0), "qb_plan_set_pairing")
+
     def config(self):
-        """qb_plan_config: (tile E, I_3 adjoint variant) currently in use."""
-        e, v = ctypes.c_int32(), ctypes.c_int32()
-        _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v)), "qb_plan_config")
-        return {"tile": e.value, "adjoint_variant": v.value}
+        """qb_plan_config: tile E, I_3 adjoint variant and node pairing in use."""
+        e, v, pn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v), ctypes.byref(pn)),
+               "qb_plan_config")
+        return {"tile": e.value, "adjoint_variant": v.value, "paired_nodes": bool(pn.value)}
 
     def profile(self, enable=True):
         """qb_profile: bracket every launch of this plan with HIP events."""

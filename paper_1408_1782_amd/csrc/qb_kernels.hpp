@@ -365,19 +365,25 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
 // (-1 for a = 0), packed (0 + i1), (2 + i3), into i3p[cell][j].
 // c = (pi/J) w_m.  Per pair: 2 shift transforms, 8 packed convolutions of 2
 // transforms each, 2 transforms of the partner sums.
-// When the four shifted fields fit in registers next to the working field
-// (SREG), they stay there for the whole node; otherwise they go through a
-// per-workgroup buffer.  The partner sums stay in registers when they fit
-// (PAIR); where they do not (float64 with 32 elements per thread), the
-// kernel runs every node unpaired instead.
-#ifndef QB_I3_SREG_VGPRS
-#define QB_I3_SREG_VGPRS 100
-#endif
-template <typename T, int E>
+// Register plan.  One workgroup of NT threads puts NT / 256 waves on each
+// SIMD (at least one), so a thread may hold 512 / that many VGPRs (at most
+// 256).  The working field takes 2 E values; the partner sums of a row pair
+// 2 E more (PAIR: node pairing pays only while they stay in registers); the
+// four shifted fields 4 E more (SREG: otherwise they go through a
+// per-workgroup buffer).  About 48 VGPRs go to addresses and temporaries.
+// PAIR is the default; the kernel is compiled both ways and the tuner may
+// pick pairing where its partner sums spill (it can still win).
+template <typename T, int P, int E>
 struct I3Regs {
-  static constexpr bool SREG = 6 * E * (int)sizeof(T) / 4 <= QB_I3_SREG_VGPRS;
-  // node pairing pays only while the partner sums stay in registers
-  static constexpr bool PAIR = 2 * E * (int)sizeof(T) / 4 <= 64;
+  static constexpr int NT = P * (P / E);
+  static constexpr int WPS = NT / 256 > 1 ? NT / 256 : 1;
+  static constexpr int BUDGET = 512 / WPS < 256 ? 512 / WPS : 256;
+  static constexpr int F = E * (int)sizeof(T) / 4;  // VGPRs of one field
+  static constexpr bool PAIR = 2 * F + 2 * F + 48 <= BUDGET;
+  template <bool PR>
+  static constexpr bool sreg() {
+    return 2 * F + (PR ? 2 * F : 0) + 4 * F + 48 <= BUDGET;
+  }
 };
 
 template <typename T>
@@ -385,11 +391,11 @@ __device__ __forceinline__ T pick4(int i, T a, T b, T c, T d) {
   return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
 }
 
-template <typename T, int P, int E>
+template <typename T, int P, int E, bool PAIR>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_per_eu(Kern<T, P, E>::WAVES))) void k_i3(DevPlan<T> d, int ncells) {
   using K = Kern<T, P, E>;
   constexpr unsigned S = sizeof(T);
-  constexpr bool SREG = I3Regs<T, E>::SREG;
+  constexpr bool SREG = I3Regs<T, P, E>::template sreg<PAIR>();
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
@@ -406,7 +412,6 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
   T s[SREG ? 4 : 1][SREG ? E : 1];
-  constexpr bool PAIR = I3Regs<T, E>::PAIR;
   const int nnode = PAIR ? (d.M + 1) / 2 : d.M;
 #pragma unroll 1
   for (int m = 0; m < nnode; ++m) {

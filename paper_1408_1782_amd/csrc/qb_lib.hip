@@ -79,6 +79,24 @@ void gauss_legendre(int M, std::vector<double>& x, std::vector<double>& w) {
 }
 
 // elements per thread of the FFT engine; must match qb::Cfg used by the kernels
+template <typename T, int P, int E>
+constexpr bool paired_t() {
+  return qb::I3Regs<T, P, E>::PAIR;
+}
+
+// default node pairing of the I_3 kernel of this tile (register plan)
+bool i3_paired(int precision, int P, int E) {
+  const bool d = precision == QB_F64;
+  switch (P) {
+    case 32: return E == 8 ? (d ? paired_t<double, 32, 8>() : paired_t<float, 32, 8>())
+                           : (d ? paired_t<double, 32, 16>() : paired_t<float, 32, 16>());
+    case 64: return E == 16 ? (d ? paired_t<double, 64, 16>() : paired_t<float, 64, 16>())
+                            : (d ? paired_t<double, 64, 32>() : paired_t<float, 64, 32>());
+    default: return E == 16 ? (d ? paired_t<double, 128, 16>() : paired_t<float, 128, 16>())
+                            : (d ? paired_t<double, 128, 32>() : paired_t<float, 128, 32>());
+  }
+}
+
 int cfg_E(int precision, int P) {
   if (precision == QB_F64) return P == 32 ? qb::Cfg<double, 32>::E : (P == 64 ? qb::Cfg<double, 64>::E : qb::Cfg<double, 128>::E);
   return P == 32 ? qb::Cfg<float, 32>::E : (P == 64 ? qb::Cfg<float, 64>::E : qb::Cfg<float, 128>::E);
@@ -178,6 +196,7 @@ bool select_tile(qb_plan_s* pl, int E) {
   pl->E = E;
   pl->TPR = pl->P / E;
   pl->NT = pl->P * pl->TPR;
+  pl->i3_pair = i3_paired(pl->prob.precision, pl->P, E);
   return true;
 }
 
@@ -663,9 +682,11 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
   const TuneKey key{p.precision, p.N, p.J, p.M, ncells};
   auto it = tune_cache().find(key);
   int best = cands[0];
+  bool best_pair = i3_paired(p.precision, pl->P, best);
   if (it != tune_cache().end()) {
-    best = it->second;
-  } else if (cands.size() > 1) {
+    best = it->second / 2;
+    best_pair = it->second % 2 == 1;
+  } else {
     T* w = (T*)pl->st0;
     T* c = (T*)pl->cbuf;
     if (!hip_ok(hipMemsetAsync(w, 0, (size_t)4 * p.Nx * p.N * p.N * sizeof(T), s), "hipMemsetAsync"))
@@ -674,27 +695,31 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
     pl->profiling = false;
     hipEvent_t a = pl->event(), b = pl->event();
     float best_ms = 1e30f;
-    for (int E : cands) {
-      if (!select_tile<T>(pl, E)) return QB_EHIP;
-      if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;  // warm-up
-      (void)hipEventRecord(a, s);
-      for (int r = 0; r < 2; ++r)
-        if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;
-      (void)hipEventRecord(b, s);
-      if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, a, b);
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = E;
+    for (int E : cands)
+      for (int pair = 0; pair < 2; ++pair) {
+        if (!select_tile<T>(pl, E)) return QB_EHIP;
+        pl->i3_pair = pair == 1;
+        if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;  // warm-up
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < 2; ++r)
+          if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;
+        (void)hipEventRecord(b, s);
+        if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = E;
+          best_pair = pair == 1;
+        }
       }
-    }
     pl->pool.push_back(a);
     pl->pool.push_back(b);
     pl->profiling = prof;
-    tune_cache()[key] = best;
+    tune_cache()[key] = 2 * best + (best_pair ? 1 : 0);
   }
   if (!select_tile<T>(pl, best)) return QB_EHIP;
+  pl->i3_pair = best_pair;
   if (chosen) *chosen = best;
   if (pl->adjoint) {
     // the two I_3 adjoint kernels (memory or register accumulators)
@@ -1076,16 +1101,23 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E) {
   return ok ? QB_OK : QB_EHIP;
 }
 
+qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired) {
+  if (!plan || paired < 0 || paired > 1) return QB_EINVAL;
+  plan->i3_pair = paired == 1;
+  return QB_OK;
+}
+
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant) {
   if (!plan || variant < 0 || variant > 2) return QB_EINVAL;
   plan->vjp_variant = variant;
   return QB_OK;
 }
 
-qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant) {
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes) {
   if (!plan) return QB_EINVAL;
   if (tile) *tile = plan->E;
   if (adjoint_variant) *adjoint_variant = plan->vjp_variant;
+  if (paired_nodes) *paired_nodes = plan->i3_pair ? 1 : 0;
   return QB_OK;
 }
 

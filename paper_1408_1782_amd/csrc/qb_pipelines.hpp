@@ -16,7 +16,10 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, 
   hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
   pl->end(id, s);
   id = pl->begin(QB_K_I3, s);
-  hipLaunchKernelGGL((qb::k_i3<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+  if (pl->i3_pair)
+    hipLaunchKernelGGL((qb::k_i3<T, P, E, true>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+  else
+    hipLaunchKernelGGL((qb::k_i3<T, P, E, false>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
   const size_t nel = (size_t)ncells * P * P;
   hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);

@@ -22,6 +22,7 @@ struct qb_plan_s {
   qb_problem prob;
   int P, E, NT, TPR;
   int wcells;  // cells per collision launch (the workspace holds this many)
+  bool i3_pair = true;  // I_3 kernel pairs the Gauss-Legendre nodes (tuned; default per tile)
   int vjp_variant = 0;  // I_3 adjoint: 0 accumulators in memory, 1 Y in registers, 2 Y and w_bar (tuned)
   size_t bytes = 0;
   std::vector<void*> allocs;

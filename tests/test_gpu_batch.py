@@ -42,15 +42,19 @@ def problem(w, precision, J, M, Nx=None):
                       qb.BC.from_workload(w.left), qb.BC.from_workload(w.right))
 
 
+@pytest.mark.parametrize("paired", [True, False])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 @pytest.mark.parametrize("N,E", [(16, 16), (16, 8), (32, 32), (32, 16), (64, 32), (64, 16)])
-def test_every_tile_matches_oracle(precision, N, E):
+def test_every_tile_matches_oracle(precision, N, E, paired):
+    """Every tile shape, I_3 with and without node pairing (odd M: the
+    middle node runs alone)."""
     import torch
     import paper_1408_1782_amd as qb
     w = wl.config(2, Nx=2, N=N)
     J, M = 6, 5
     plan = qb.Plan(problem(w, precision, J, M))
     plan.set_tile(E)
+    plan.set_pairing(paired)
     C = plan.collision(to_dev(w.W0, precision))
     torch.cuda.synchronize()
     t = oc.Tables(N, w.L, w.R, J, M)
