@@ -371,6 +371,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
 // 2 E more (PAIR: node pairing pays only while they stay in registers); the
 // four shifted fields 4 E more (SREG: otherwise they go through a
 // per-workgroup buffer).  About 48 VGPRs go to addresses and temporaries.
+// (The thresholds were checked against the compiler's register reports for
+// every compiled tile: no scratch spills except where noted.)
 // PAIR is the default; the kernel is compiled both ways and the tuner may
 // pick pairing where its partner sums spill (it can still win).
 template <typename T, int P, int E>
@@ -380,9 +382,11 @@ struct I3Regs {
   static constexpr int BUDGET = 512 / WPS < 256 ? 512 / WPS : 256;
   static constexpr int F = E * (int)sizeof(T) / 4;  // VGPRs of one field
   static constexpr bool PAIR = 2 * F + 2 * F + 48 <= BUDGET;
+  // the transforms need about 2 E more values of temporaries once the
+  // shifted fields live in registers too
   template <bool PR>
   static constexpr bool sreg() {
-    return 2 * F + (PR ? 2 * F : 0) + 4 * F + 48 <= BUDGET;
+    return 2 * F + (PR ? 2 * F : 0) + 4 * F + 2 * F + 48 <= BUDGET;
   }
 };
 
@@ -396,6 +400,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   using K = Kern<T, P, E>;
   constexpr unsigned S = sizeof(T);
   constexpr bool SREG = I3Regs<T, P, E>::template sreg<PAIR>();
+  // the current row pair's two shifted fields in registers for the nu loop
+  // (saves two field reads per convolution); fits the unpaired kernel with
+  // at most 16 registers per field
+  constexpr bool AREG = !SREG && !PAIR && I3Regs<T, P, E>::F <= 16;
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
@@ -458,6 +466,15 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         for (int n = 0; n < E; ++n) pa[n] = pb[n] = 0;
       }
       const T sa_sign = m0 == 0 ? (T)-1 : (T)1;
+      // the row pair's shifted fields, in registers for the nu loop
+      T ra[AREG ? E : 1], rbv[AREG ? E : 1];
+      if constexpr (AREG) {
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          ra[AREG ? n : 0] = bld<T>(rb, vo, (m0 * K::FSZ + n * K::NT) * S);
+          rbv[AREG ? n : 0] = bld<T>(rb, vo, (m1 * K::FSZ + n * K::NT) * S);
+        }
+      }
 #pragma unroll 1
       for (int nu = 0; nu < 4; ++nu) {
         T zr[E], zi[E];
@@ -492,6 +509,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           if constexpr (SREG) {
             sa = mp == 0 ? s[0][n] : s[SREG ? 2 : 0][n];
             sb = mp == 0 ? s[SREG ? 1 : 0][n] : s[SREG ? 3 : 0][n];
+          } else if constexpr (AREG) {
+            sa = ra[AREG ? n : 0];
+            sb = rbv[AREG ? n : 0];
           } else {
             sa = bld<T>(rb, vo, (m0 * K::FSZ + o) * S);
             sb = bld<T>(rb, vo, (m1 * K::FSZ + o) * S);
