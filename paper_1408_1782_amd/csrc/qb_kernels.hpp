@@ -109,6 +109,35 @@ __device__ __forceinline__ void bst(rsrc_t r, T v, unsigned voff, unsigned soff)
   }
 }
 
+// Buffer-to-LDS copy of one float field in the engine's element order:
+// element n of thread t (byte n NT 4 + 4 t past soff) lands in lds[n NT + t].
+// Each load writes the 64 lanes of a wavefront to 64 consecutive LDS words
+// starting at a wave-uniform address, so a thread later reads only words
+// its own wavefront wrote: the wait below, not a barrier, orders them.
+template <typename T, int NT, int E>
+__device__ __forceinline__ void fetch_lds(rsrc_t r, T* lds, unsigned voff, unsigned soff) {
+  static_assert(sizeof(T) == 4, "buffer-to-LDS loads of 4-byte elements");
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned lb = (unsigned)(size_t)(__attribute__((address_space(3))) T*)lds + 256u * wave;
+  unsigned sb = soff;
+  // opaque here, so the per-element scalar offsets below are formed at the
+  // loads instead of being hoisted out of the caller's loops (which would
+  // hold 2 E scalar registers for the whole kernel)
+  __asm__ volatile("" : "+s"(lb), "+s"(sb));
+#pragma unroll
+  for (int n = 0; n < E; ++n)
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(size_t)(lb + n * NT * 4), 4, voff, sb + n * NT * 4, 0, 0);
+}
+// Wait until every buffer load of this wavefront (the LDS copies included)
+// has completed; returns the thread index through the wait so that LDS
+// reads addressed with it cannot move above the wait.
+__device__ __forceinline__ unsigned lds_fetch_wait() {
+  unsigned t = threadIdx.x;
+  __asm__ volatile("s_waitcnt vmcnt(0)" : "+v"(t));
+  return t;
+}
+
 // XCD-aware block order: consecutive logical tasks share an XCD (its L2).
 __device__ __forceinline__ int xcd_task(int b, int nb) {
   if ((nb & 7) != 0) return b;
@@ -388,6 +417,14 @@ struct I3Regs {
   static constexpr bool sreg() {
     return 2 * F + (PR ? 2 * F : 0) + 4 * F + 2 * F + 48 <= BUDGET;
   }
+  // one float32 field of LDS beside the transpose buffer, where it fits in
+  // the 160 KB of a compute unit and one workgroup fills the compute unit
+  // anyway (P = 128): the staging buffer of the accumulator prefetches
+  template <bool PR, int LDS_SCALARS>
+  static constexpr bool lds_field() {
+    return PR && !sreg<PR>() && P == 128 && sizeof(T) == 4 &&
+           (LDS_SCALARS + P * P) * (int)sizeof(T) <= 160 * 1024;
+  }
 };
 
 template <typename T>
@@ -404,7 +441,12 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   // (saves two field reads per convolution); fits the unpaired kernel with
   // at most 16 registers per field
   constexpr bool AREG = !SREG && !PAIR && I3Regs<T, P, E>::F <= 16;
+  // PF: the accumulator field read back after a convolution is fetched
+  // into LDS (buffer-to-LDS loads, no registers) before the convolution
+  // starts, so its latency hides behind the transforms
+  constexpr bool PF = I3Regs<T, P, E>::template lds_field<PAIR, K::LDS>();
   __shared__ T smem[K::LDS];
+  __shared__ T pf[PF ? K::FSZ : 1];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
   const int task = xcd_task(blockIdx.x, gridDim.x);
@@ -475,8 +517,12 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           rbv[AREG ? n : 0] = bld<T>(rb, vo, (m1 * K::FSZ + n * K::NT) * S);
         }
       }
+      const bool first = m == 0 && mp == 0;
 #pragma unroll 1
       for (int nu = 0; nu < 4; ++nu) {
+        // (fetched on the first pass too, where the values go unused: a
+        // branch here would split the block the scheduler works on)
+        if constexpr (PF) fetch_lds<T, K::NT, E>(ro, pf, vo, nu * K::FSZ * S);
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
@@ -500,8 +546,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         }
         eng.inv2(zr, zi);
         const T e0 = m0 == 0 ? wgt : -wgt;
-        const bool first = m == 0 && mp == 0;
         const T ew = nu == 0 ? wgt : -wgt;  // c eta_nu
+        const unsigned pt = PF ? lds_fetch_wait() : 0u;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
@@ -518,7 +564,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           }
           const unsigned off = (nu * K::FSZ + o) * S;
           T v = e0 * sa * zr[n] - wgt * sb * zi[n];
-          if (!first) v += bld<T>(ro, vo, off);
+          if (!first) v += PF ? pf[PF ? o + pt : 0] : bld<T>(ro, vo, off);
           bst<T>(ro, v, vo, off);
           if constexpr (PAIR) {
             if (paired) {
@@ -539,7 +585,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           zr[n] = pa[PAIR ? n : 0];
           zi[n] = pb[PAIR ? n : 0];
         }
+        if constexpr (PF) fetch_lds<T, K::NT, E>(rp, pf, vo, fr * S);
         eng.fwd2(zr, zi);
+        const unsigned pt = PF ? lds_fetch_wait() : 0u;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           const unsigned o = k * K::NT;
@@ -548,7 +596,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           T xr, xi;
           cmul(zr[k], zi[k], er, -ei, xr, xi);
           if (m != 0) {
-            xr += bld<T>(rp, vo, (fr + o) * S);
+            xr += PF ? pf[PF ? o + pt : 0] : bld<T>(rp, vo, (fr + o) * S);
             xi += bld<T>(rp, vo, (fi + o) * S);
           }
           bst<T>(rp, xr, vo, (fr + o) * S);
