@@ -32,6 +32,10 @@ What it computes, and where the paper defines it:
 * ``step``       -- the time-splitting step of Sec. 4 (half transport,
                     collision + magnetic field, half transport) and the
                     fluid moments (eq. density, velocity, internal_energy).
+* ``diagnostics``-- local entropy (eq. entropy_def), the entropy
+                    production density of the H-theorem, the quantum
+                    relative entropy (eq. relentropy_hom), the eigenvalue
+                    range and the local Fermi-Dirac fit of Sec. 5.
 * ``adjoint``    -- reverse-mode derivatives of the above (the transpose of
                     each forward step, run backwards): C'(w)^T lam, the
                     transport and splitting steps, and the gradient of a
