@@ -137,6 +137,37 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Diagnostics of a state (Sec. 2 and Sec. 5), float64 whatever the plan's
+ * precision, one row of QB_DIAG_FIELDS values per cell:
+ *   0  local entropy S = -h^2 sum_v tr[W log W + W~ log W~], W~ = 1 - W
+ *      (eq. entropy_def);
+ *   1  entropy production density -h^2 sum_v tr[(log W - log W~) C] (the
+ *      integrand of the H-theorem; its sum times dx is d/dt of the total
+ *      entropy under dW/dt = C); 0 when C is NULL;
+ *   2  relative entropy h^2 sum_v tr[W (log W - log F) + W~ (log W~ - log F~)]
+ *      to the Fermi-Dirac state F = W_FD(global) at rest (eq. relentropy_hom;
+ *      times dx summed over cells: eq. relentropy_inhom); 0 when global is NULL;
+ *   3  the same relative entropy to the local fit W_FD,loc (eq. relentropy_local);
+ *   4, 5  smallest and largest eigenvalue of W(v) over the cell (unclamped);
+ *   6..10 the local fit: kT, mu_up, mu_down, u_x, u_y.  u = momentum /
+ *      density (eq. velocity); the per-spin densities are the eigenvalues
+ *      r_up >= r_down of the spin density h^2 sum_v W, the spin basis its
+ *      eigenbasis; kT and mu_s solve r_s = 2 pi kT log(1 + e^{mu_s/kT}) and
+ *      eps = e/n - |u|^2/2 = eps_FD (eq. momentsFermiDirac).
+ * Eigenvalues are clamped into [0, 1] inside the logarithms and log x reads
+ * log(max(x, 1e-300)).  The fit fields and field 3 are NaN where no
+ * Fermi-Dirac state matches: r_down <= 0, or kT below r_up / (1200 pi).
+ * W, C: [Nx][N][N][2][2] complex of the plan's precision (C may be NULL,
+ * e.g. C = qb_collision(W)); global: host struct or NULL (its U need only
+ * have a nonzero first column, the spin-up direction); out: float64
+ * [Nx][QB_DIAG_FIELDS] device array.  QB_EINVAL for null W / out, or a
+ * global state with inv_kT <= 0, non-finite values or a zero first column.
+ * ------------------------------------------------------------------------- */
+#define QB_DIAG_FIELDS 11
+qb_status qb_diagnostics(qb_plan plan, const void* W, const void* C, const qb_fd* global, double* out,
+                         void* stream);
+
+/* ---------------------------------------------------------------------------
  * FFT tile shapes.  Every padded-grid transform runs in one workgroup that
  * holds the P x P field in registers, E elements per thread and P / E
  * threads per line.  Compiled shapes: P = 32: E = 16 (default), 8;
@@ -266,7 +297,8 @@ typedef enum {
   QB_K_MOMENTS = 6,
   QB_K_I3_ADJOINT = 7, /* transpose of the I_3 kernel */
   QB_K_ADJOINT = 8,    /* the other reverse-mode kernels */
-  QB_K_COUNT = 9
+  QB_K_DIAGNOSTICS = 9,
+  QB_K_COUNT = 10
 } qb_kernel;
 qb_status qb_profile(qb_plan plan, int32_t enable);
 qb_status qb_profile_read(qb_plan plan, int32_t kernel, double* total_ms, int64_t* launches);

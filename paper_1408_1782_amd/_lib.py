@@ -16,7 +16,10 @@ QB_F64, QB_F32 = 0, 1
 QB_PERIODIC, QB_DIRICHLET, QB_MAXWELL = 0, 1, 2
 _KINDS = {"periodic": QB_PERIODIC, "dirichlet": QB_DIRICHLET, "maxwell": QB_MAXWELL}
 KERNELS = {"dft_in": 0, "terms": 1, "i3": 2, "combine": 3, "transport": 4, "heun": 5, "moments": 6,
-           "i3_adjoint": 7, "adjoint": 8}
+           "i3_adjoint": 7, "adjoint": 8, "diagnostics": 9}
+QB_DIAG_FIELDS = 11
+DIAG_NAMES = ("entropy", "entropy_production", "rel_entropy_global", "rel_entropy_local", "eig_min",
+              "eig_max", "kT", "mu_up", "mu_down", "u_x", "u_y")
 
 # names the header declares (checked by the CPU tests)
 EXPORTS = (
@@ -27,6 +30,7 @@ EXPORTS = (
     "qb_transport_step",
     "qb_step",
     "qb_moments",
+    "qb_diagnostics",
     "qb_plan_enable_adjoint",
     "qb_collision_vjp",
     "qb_transport_vjp",
@@ -111,6 +115,8 @@ def _declare(lib):
     lib.qb_step.restype = i32
     lib.qb_moments.argtypes = [vp, vp, vp, vp]
     lib.qb_moments.restype = i32
+    lib.qb_diagnostics.argtypes = [vp, vp, vp, ctypes.POINTER(_FD), vp, vp]
+    lib.qb_diagnostics.restype = i32
     lib.qb_plan_enable_adjoint.argtypes = [vp]
     lib.qb_plan_enable_adjoint.restype = i32
     lib.qb_collision_vjp.argtypes = [vp, vp, vp, vp, i32, vp]
@@ -387,6 +393,30 @@ class Plan:
         _check(self.lib.qb_adjoint_step(self.handle, wp, rp, self._field(B), float(dt), _ptr(lam_next), _ptr(lam),
                                         gp, _stream()), "qb_adjoint_step")
         return lam
+
+    def diagnostics(self, W, C=None, fd=None, out=None):
+        """qb_diagnostics: float64 [Nx, QB_DIAG_FIELDS] per-cell entropy,
+        entropy production (with C = C[W]), relative entropies to the global
+        Fermi-Dirac state fd = (inv_kT, mu_up, mu_down, U) and to the local
+        fit, eigenvalue range and the fit itself (columns: DIAG_NAMES)."""
+        import torch
+
+        self._check_state(W)
+        cp = ctypes.c_void_p(0)
+        if C is not None:
+            self._check_state(C)
+            cp = _ptr(C)
+        gp = None
+        if fd is not None:
+            inv_kT, mu_up, mu_down, U = fd
+            gp = BC("dirichlet", inv_kT, mu_up, mu_down, U)._c().state
+        if out is None:
+            out = torch.empty((self.problem.Nx, QB_DIAG_FIELDS), dtype=torch.float64, device=W.device)
+        elif out.dtype != torch.float64 or tuple(out.shape) != (self.problem.Nx, QB_DIAG_FIELDS) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous CUDA float64 tensor [Nx, QB_DIAG_FIELDS]")
+        _check(self.lib.qb_diagnostics(self.handle, _ptr(W), cp, None if gp is None else ctypes.byref(gp), _ptr(out),
+                                       _stream()), "qb_diagnostics")
+        return out
 
     def moments(self, W, out=None):
         """qb_moments: float64 [Nx, 7] moments of W."""

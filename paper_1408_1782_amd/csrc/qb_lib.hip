@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "qb_plan.hpp"
+#include "qb_diag.hpp"
 
 namespace {
 thread_local std::string g_last_error;
@@ -584,6 +585,16 @@ qb_status do_moments(qb_plan_s* pl, const void* W, double* mom, hipStream_t s) {
 }
 
 template <typename T>
+qb_status do_diagnostics(qb_plan_s* pl, const void* W, const void* C, const qb::FdGlobal& g, double* out,
+                         hipStream_t s) {
+  const qb_problem& p = pl->prob;
+  const int id = pl->begin(QB_K_DIAGNOSTICS, s);
+  hipLaunchKernelGGL((qb::k_diagnostics<T>), dim3(p.Nx), dim3(256), 0, s, (const T*)W, (const T*)C, g, out, p.N, p.L);
+  pl->end(id, s);
+  return hip_ok(hipGetLastError(), "diagnostics launch") ? QB_OK : QB_EHIP;
+}
+
+template <typename T>
 qb_status do_collision_vjp(qb_plan_s* pl, const void* W, const void* lam, void* G, int ncells, hipStream_t s) {
   T* w = (T*)pl->wn;
   T* g = (T*)pl->g0;
@@ -1049,6 +1060,30 @@ qb_status qb_moments(qb_plan plan, const void* W, double* mom, void* stream) {
   return do_moments<float>(plan, W, mom, s);
 }
 
+qb_status qb_diagnostics(qb_plan plan, const void* W, const void* C, const qb_fd* global, double* out,
+                         void* stream) {
+  if (!plan || !W || !out) return QB_EINVAL;
+  qb::FdGlobal g{};
+  if (global) {
+    // Bloch vector of the spin-up projector: first column (a, b) of U
+    const double ar = global->U_re[0], ai = global->U_im[0], br = global->U_re[2], bi = global->U_im[2];
+    const double nn = ar * ar + ai * ai + br * br + bi * bi;
+    if (!(global->inv_kT > 0.0) || !std::isfinite(global->inv_kT) || !std::isfinite(global->mu_up) ||
+        !std::isfinite(global->mu_down) || !(nn > 0.0) || !std::isfinite(nn))
+      return QB_EINVAL;
+    g.inv_kT = global->inv_kT;
+    g.mu_up = global->mu_up;
+    g.mu_down = global->mu_down;
+    g.n[0] = 2.0 * (ar * br + ai * bi) / nn;  // 2 Re(conj(a) b)
+    g.n[1] = 2.0 * (ar * bi - ai * br) / nn;  // 2 Im(conj(a) b)
+    g.n[2] = (ar * ar + ai * ai - br * br - bi * bi) / nn;
+    g.valid = 1;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_diagnostics<double>(plan, W, C, g, out, s);
+  return do_diagnostics<float>(plan, W, C, g, out, s);
+}
+
 const char* qb_strerror(qb_status status) {
   switch (status) {
     case QB_OK: return "ok";
@@ -1253,6 +1288,6 @@ qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, 
   return hip_ok(hipGraphLaunch(batch->exec, s), "hipGraphLaunch") ? QB_OK : QB_EHIP;
 }
 
-int32_t qb_version(void) { return 300; }
+int32_t qb_version(void) { return 310; }
 
 }  // extern "C"
