@@ -18,6 +18,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
@@ -267,6 +269,86 @@ def cpu_baseline(wl):
     }
 
 
+def _pauli_np(C):
+    """Pauli components c_mu = (1/2) Re tr(sigma_mu C) of [..., 2, 2] -> [4, ...]."""
+    return np.stack([0.5 * (C[..., 0, 0] + C[..., 1, 1]).real, 0.5 * (C[..., 0, 1] + C[..., 1, 0]).real,
+                     0.5 * (C[..., 1, 0] - C[..., 0, 1]).imag, 0.5 * (C[..., 0, 0] - C[..., 1, 1]).real])
+
+
+def _fourier(c):
+    """Mean-value Fourier coefficients on Xi of the components c[4, N, N],
+    centred (frequency xi at index xi + N/2 on each axis)."""
+    N = c.shape[-1]
+    return np.fft.fftshift(np.fft.fft2(c), axes=(-2, -1)) / (N * N)
+
+
+def rel_l1(c, ref):
+    """sum_j ||C_j - C_ref,j||_1 / ||C_ref,j||_1 over the Pauli components
+    whose reference is not zero (C_c,0 vanishes identically; its rounding
+    noise, below 1e-12 of the largest component, is skipped), L1 norms of
+    the Fourier coefficients (Sec. 5.1).  For a smaller grid than the
+    reference the coefficients are compared on the common frequencies and
+    the reference's other coefficients count as error."""
+    a, b = _fourier(c), _fourier(ref)
+    n, m = a.shape[-1], b.shape[-1]
+    o = (m - n) // 2
+    d = b.copy()
+    d[:, o:o + n, o:o + n] -= a
+    norms = [np.abs(b[j]).sum() for j in range(4)]
+    err = 0.0
+    for j in range(4):
+        if norms[j] > 1e-12 * max(norms):
+            err += np.abs(d[j]).sum() / norms[j]
+    return err
+
+
+def run_convergence(precision="f64"):
+    """Convergence of C_c and C_d on the validation state (Sec. 5.1) with
+    the number of angles J, Gauss-Legendre radii M and grid points N,
+    against J = 72, M = 72 and N = 64 (the largest grid here)."""
+    import torch
+    import paper_1408_1782_amd as qb
+    import workloads
+
+    L, R = workloads.L_BOX, workloads.R_TRUNC
+    cache = {}
+
+    def parts(N, J, M):
+        key = (N, J, M)
+        if key not in cache:
+            plan = qb.Plan(qb.Problem(1, N, J, M, L, R, precision))
+            cd = torch.complex128 if precision == "f64" else torch.complex64
+            W = torch.from_numpy(workloads.validation_state(N, L)[None]).to(cd).cuda().contiguous()
+            out = {}
+            for t in ("conservative", "dissipative"):
+                plan.set_terms(t)
+                out[t] = _pauli_np(plan.collision(W).cpu().numpy()[0].astype(np.complex128))
+            plan.close()
+            cache[key] = out
+        return cache[key]
+
+    def sweep(vals, key, ref_key):
+        ref = parts(*ref_key)
+        rows = []
+        for v in vals:
+            got = parts(*key(v))
+            rows.append({"value": v, "C_c": rel_l1(got["conservative"], ref["conservative"]),
+                         "C_d": rel_l1(got["dissipative"], ref["dissipative"])})
+            log(f"[convergence] {key(v)} vs {ref_key}: C_c {rows[-1]['C_c']:.3e}  C_d {rows[-1]['C_d']:.3e}")
+        return rows
+
+    grid = [8, 12, 16, 20, 24, 28, 32, 40, 48, 56, 64]
+    return {
+        "study": "collision convergence on the validation state (Sec. 5.1)",
+        "precision": precision, "L": L, "R": R,
+        "J": {"fixed": {"N": 32, "M": 32}, "reference": 72, "rows": sweep(grid, lambda v: (32, v, 32), (32, 72, 32))},
+        "M": {"fixed": {"N": 32, "J": 32}, "reference": 72, "rows": sweep(grid, lambda v: (32, 32, v), (32, 32, 72))},
+        "N": {"fixed": {"J": 32, "M": 72}, "reference": 64,
+              "rows": sweep([16, 32], lambda v: (v, 32, 72), (64, 32, 72))},
+        "error": "sum over Pauli components of relative L1 norms of Fourier coefficients",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,11 +365,16 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=64, help="problems in the uneven batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (scale for HBM byte counters)")
+    ap.add_argument("--convergence", action="store_true",
+                    help="print the J / M / N convergence study of C_c and C_d instead of the bench line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.convergence:
+        print(json.dumps(run_convergence()), flush=True)
+        return
 
     import workloads
 

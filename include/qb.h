@@ -137,6 +137,20 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Term selection (Sec. 3.2 and the validation of Sec. 5.1, which measures
+ * the conservative and the dissipative part separately): qb_collision and
+ * qb_step assemble C = w_c C_c + w_d C_d with (w_c, w_d) = (1, 0) for
+ * QB_TERMS_CONSERVATIVE, (0, 1) for QB_TERMS_DISSIPATIVE and (1, 1) for
+ * QB_TERMS_ALL (the default).  The reverse mode (qb_collision_vjp,
+ * qb_adjoint_step) returns QB_ENOTSUP unless the plan uses QB_TERMS_ALL.
+ * QB_EINVAL for other values.
+ * ------------------------------------------------------------------------- */
+#define QB_TERMS_CONSERVATIVE 1
+#define QB_TERMS_DISSIPATIVE 2
+#define QB_TERMS_ALL 3
+qb_status qb_plan_set_terms(qb_plan plan, int32_t terms);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics of a state (Sec. 2 and Sec. 5), float64 whatever the plan's
  * precision, one row of QB_DIAG_FIELDS values per cell:
  *   0  local entropy S = -h^2 sum_v tr[W log W + W~ log W~], W~ = 1 - W

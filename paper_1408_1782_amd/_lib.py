@@ -42,6 +42,7 @@ EXPORTS = (
     "qb_plan_config",
     "qb_plan_set_adjoint_variant",
     "qb_plan_set_pairing",
+    "qb_plan_set_terms",
     "qb_batch_create",
     "qb_batch_destroy",
     "qb_batch_bytes",
@@ -138,6 +139,8 @@ def _declare(lib):
     lib.qb_plan_set_adjoint_variant.argtypes = [vp, i32]
     lib.qb_plan_set_adjoint_variant.restype = i32
     lib.qb_plan_set_pairing.argtypes = [vp, i32]
+    lib.qb_plan_set_terms.argtypes = [vp, i32]
+    lib.qb_plan_set_terms.restype = i32
     lib.qb_plan_set_pairing.restype = i32
     lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
     lib.qb_batch_create.restype = i32
@@ -449,6 +452,13 @@ class Plan:
     def set_pairing(self, paired):
         """qb_plan_set_pairing: I_3 kernel with or without node pairing."""
         _check(self.lib.qb_plan_set_pairing(self.handle, 1 if paired else 0), "qb_plan_set_pairing")
+
+    TERMS = {"conservative": 1, "dissipative": 2, "all": 3}
+
+    def set_terms(self, terms):
+        """qb_plan_set_terms: assemble only C_c ('conservative'), only C_d
+        ('dissipative') or both ('all', the default)."""
+        _check(self.lib.qb_plan_set_terms(self.handle, self.TERMS[terms]), "qb_plan_set_terms")
 
     def config(self):
         """qb_plan_config: tile E, I_3 adjoint variant and node pairing in use."""

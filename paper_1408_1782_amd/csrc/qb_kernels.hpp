@@ -36,6 +36,7 @@ template <typename T>
 struct DevPlan {
   int Nx, N, J, M, P;
   T L;
+  T wc, wd;  // weights of C_c and C_d in the assembled C (term selection; 1, 1 for the full operator)
   // tables, col-spec layout [J][P*P] unless noted
   const T* tw;     // [P][2] (cos, sin)(2 pi i / P)
   const T* phip;   // phi_R(b . theta'_j)                       (I_1 inner)
@@ -643,10 +644,11 @@ __global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
   T* r = d.i3sum + cell * per + e;
   // A: 2 <w3, w4>_eta (1 - W1); B: -2 <w3, w4>_eta (eta w2).sigma;
   // Cq: f0(v+u) {W1, (eta w2).sigma};  C_c,k = -2 eps_klm A^G_l w_m
-  r[0] = pi * (two * Sv * ((T)1 - w0) - two * b[0] + two * (y0 * w0 - y1 * w1 - y2 * w2 - y3 * w3));
-  r[fsz] = -two * (g2 * w3 - g3 * w2) + pi * (-two * Sv * w1 + two * b[1] + two * (y0 * w1 - y1 * w0));
-  r[2 * fsz] = -two * (g3 * w1 - g1 * w3) + pi * (-two * Sv * w2 + two * b[2] + two * (y0 * w2 - y2 * w0));
-  r[3 * fsz] = -two * (g1 * w2 - g2 * w1) + pi * (-two * Sv * w3 + two * b[3] + two * (y0 * w3 - y3 * w0));
+  const T pd = d.wd * pi, wc = d.wc;
+  r[0] = pd * (two * Sv * ((T)1 - w0) - two * b[0] + two * (y0 * w0 - y1 * w1 - y2 * w2 - y3 * w3));
+  r[fsz] = -wc * two * (g2 * w3 - g3 * w2) + pd * (-two * Sv * w1 + two * b[1] + two * (y0 * w1 - y1 * w0));
+  r[2 * fsz] = -wc * two * (g3 * w1 - g1 * w3) + pd * (-two * Sv * w2 + two * b[2] + two * (y0 * w2 - y2 * w0));
+  r[3 * fsz] = -wc * two * (g1 * w2 - g2 * w1) + pd * (-two * Sv * w3 + two * b[3] + two * (y0 * w3 - y3 * w0));
 }
 
 // ------------------------------------------------------------------ combine
@@ -681,7 +683,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_combine(DevPlan<T> d, T
     const int bx = centered<P>(eng.line);
     const bool kx_in = bx > -N / 2 && bx < N / 2;
     const T sc = (T)1 / (T)(P * P);
-    const T tp = (T)(2.0 * kPi);  // B term of the partner nodes: pi * 2 * (sign folded in)
+    const T tp = d.wd * (T)(2.0 * kPi);  // B term of the partner nodes: pi * 2 * (sign folded in)
 #pragma unroll
     for (int k = 0; k < E; ++k) {
       const unsigned o = k * K::NT;

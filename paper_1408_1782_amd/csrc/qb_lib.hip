@@ -1027,6 +1027,7 @@ qb_status qb_step_trace(qb_plan plan, void* W, const double* B, double dt, int32
 qb_status qb_collision_vjp(qb_plan plan, const void* W, const void* lam, void* G, int32_t ncells, void* stream) {
   if (!plan || !W || !lam || !G || ncells < 1) return QB_EINVAL;
   if (ncells > plan->prob.Nx || !plan->adjoint) return QB_EWORKSPACE;
+  if (plan->term_sel != QB_TERMS_ALL) return QB_ENOTSUP;
   hipStream_t s = (hipStream_t)stream;
   if (plan->prob.precision == QB_F64) return do_collision_vjp<double>(plan, W, lam, G, ncells, s);
   return do_collision_vjp<float>(plan, W, lam, G, ncells, s);
@@ -1046,6 +1047,7 @@ qb_status qb_adjoint_step(qb_plan plan, const void* W, const void* record, const
                           const void* lam_next, void* lam, double* gB, void* stream) {
   if (!plan || (!W && !record) || !lam_next || !lam) return QB_EINVAL;
   if (!plan->adjoint) return QB_EWORKSPACE;
+  if (plan->term_sel != QB_TERMS_ALL) return QB_ENOTSUP;
   qb_status st = check_cfl(plan, 0.5 * dt);
   if (st != QB_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1134,6 +1136,12 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E) {
   if (std::find(c.begin(), c.end(), (int)E) == c.end()) return QB_ENOTSUP;
   const bool ok = plan->prob.precision == QB_F64 ? select_tile<double>(plan, E) : select_tile<float>(plan, E);
   return ok ? QB_OK : QB_EHIP;
+}
+
+qb_status qb_plan_set_terms(qb_plan plan, int32_t terms) {
+  if (!plan || terms < QB_TERMS_CONSERVATIVE || terms > QB_TERMS_ALL) return QB_EINVAL;
+  plan->term_sel = terms;
+  return QB_OK;
 }
 
 qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired) {

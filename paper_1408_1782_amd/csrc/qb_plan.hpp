@@ -24,6 +24,7 @@ struct qb_plan_s {
   int wcells;  // cells per collision launch (the workspace holds this many)
   bool i3_pair = true;  // I_3 kernel pairs the Gauss-Legendre nodes (tuned; default per tile)
   int vjp_variant = 0;  // I_3 adjoint: 0 accumulators in memory, 1 Y in registers, 2 Y and w_bar (tuned)
+  int term_sel = 3;     // collision terms assembled: 1 C_c, 2 C_d, 3 both
   size_t bytes = 0;
   std::vector<void*> allocs;
   // quadrature tables in the FFT engine's element order, one set per tile
@@ -103,6 +104,8 @@ inline DevPlan<T> devplan(qb_plan_s* pl) {
   d.M = pl->prob.M;
   d.P = pl->P;
   d.L = (T)pl->prob.L;
+  d.wc = (pl->term_sel & 1) ? (T)1 : (T)0;
+  d.wd = (pl->term_sel & 2) ? (T)1 : (T)0;
   const qb_plan_s::TabSet& ts = pl->tabs[pl->cur_tab];
   d.tw = (const T*)ts.tw;
   d.phip = (const T*)ts.phip;

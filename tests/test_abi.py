@@ -78,3 +78,4 @@ def test_null_arguments_rejected():
     assert lib.qb_adjoint_step(None, None, None, None, 1e-3, None, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_trace_bytes(None) == 0
     assert lib.qb_diagnostics(None, None, None, None, None, None) == _lib.QB_EINVAL
+    assert lib.qb_plan_set_terms(None, 3) == _lib.QB_EINVAL

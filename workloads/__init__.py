@@ -182,3 +182,20 @@ def adjoint_loss_weight(Nx, config_id=5):
     s = rng.uniform(0.05, 0.15)
     x = cell_centres(Nx)
     return np.exp(-((x - x0) ** 2) / (2 * s * s))
+
+
+def validation_state(N, L=L_BOX):
+    """The fixed Wigner state of the validation of Sec. 5.1 (eq. validationW)
+    on the velocity grid (2L/N) Xi: [N, N, 2, 2] complex."""
+    vx, vy = np.meshgrid(velocity_axis(N, L), velocity_axis(N, L), indexing="ij")
+    w0 = (1.0 / (3 * np.pi)) * (1 + vx) * np.exp(-0.5 * (vx - 0.5) ** 2 - 0.5 * (vy + vx) ** 2)
+    w1 = (3 * np.sqrt(6 / 5) / (55 * np.pi)) * (1 - vx - vy / 6) ** 2 * np.exp(
+        -(2 * vx + vy) ** 2 / 12 - vy**2 / 10)
+    w2 = (1 / (4 * np.pi * np.sqrt(2))) * np.exp(-((vx - 1) ** 2) / 8 - vy**2 / 4)
+    w3 = (9 / (56 * np.pi)) * (1 / 3 + vx) ** 2 * np.exp(-((vx - vy) ** 2) / 8 - (vx + 2 * vy) ** 2 / 8)
+    W = np.zeros((N, N, 2, 2), np.complex128)
+    W[..., 0, 0] = w0 + w3
+    W[..., 1, 1] = w0 - w3
+    W[..., 0, 1] = w1 - 1j * w2
+    W[..., 1, 0] = w1 + 1j * w2
+    return W
