@@ -34,13 +34,39 @@ def heun(w, B, dt, L, tables):
     return 0.5 * (w + w1 + dt * rhs(w1, B, L, tables))
 
 
-def step(w, B, dt, L, R, J, M, bc_left, bc_right, tables=None):
-    """T(dt/2) o Heun(dt) o T(dt/2) for w[Nx, N, N, 4]."""
+def rotate(w, B, tau):
+    """Exact flow of the field term over time tau: dw/dt = 2 B x w (w0
+    fixed) turns the Bloch vector about B(x) by the angle 2 |B| tau
+    (Rodrigues' rotation formula)."""
+    B = np.asarray(B, np.float64)
+    nb = np.linalg.norm(B, axis=-1)
+    th = 2.0 * nb * tau
+    k = np.where(nb[:, None] > 0, B / np.where(nb > 0, nb, 1.0)[:, None], 0.0)[:, None, None, :]
+    c, s = np.cos(th)[:, None, None, None], np.sin(th)[:, None, None, None]
+    v = w[..., 1:]
+    kv = np.sum(k * v, axis=-1, keepdims=True)
+    out = w.copy()
+    out[..., 1:] = v * c + np.cross(k, v) * s + k * kv * (1.0 - c)
+    return out
+
+
+def step(w, B, dt, L, R, J, M, bc_left, bc_right, tables=None, limiter="minmod", field="heun"):
+    """T(dt/2) o Heun(dt) o T(dt/2) for w[Nx, N, N, 4].
+
+    Variants (Sec. 4): `limiter` selects the slope limiter of the transport
+    half-steps; field="rotation" takes the field term out of the Heun step
+    and applies its exact flow for dt/2 on either side of it,
+    T(dt/2) o F(dt/2) o Heun_C(dt) o F(dt/2) o T(dt/2)."""
     N = w.shape[1]
     t = tables if tables is not None else Tables(N, L, R, J, M)
-    w = tp.transport_step(w, 0.5 * dt, bc_left, bc_right, L)
-    w = heun(w, B, dt, L, t)
-    return tp.transport_step(w, 0.5 * dt, bc_left, bc_right, L)
+    w = tp.transport_step(w, 0.5 * dt, bc_left, bc_right, L, limiter)
+    if field == "rotation":
+        w = rotate(w, B, 0.5 * dt)
+        w = heun(w, np.zeros_like(np.asarray(B, np.float64)), dt, L, t)
+        w = rotate(w, B, 0.5 * dt)
+    else:
+        w = heun(w, B, dt, L, t)
+    return tp.transport_step(w, 0.5 * dt, bc_left, bc_right, L, limiter)
 
 
 def moments(w, L):

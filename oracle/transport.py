@@ -25,6 +25,32 @@ def minmod(a, b):
     return np.where(a * b > 0.0, np.where(np.abs(a) <= np.abs(b), a, b), 0.0)
 
 
+# Other slope limiters (Sec. 4 allows them; the standard choices of
+# LeVeque's finite-volume text), as slopes from the two one-sided
+# differences a = W_{j+1} - W_j and b = W_j - W_{j-1}:
+
+
+def superbee(a, b):
+    """The larger in magnitude of minmod(a, 2b) and minmod(2a, b)."""
+    s1, s2 = minmod(a, 2.0 * b), minmod(2.0 * a, b)
+    return np.where(np.abs(s1) >= np.abs(s2), s1, s2)
+
+
+def monotonized_central(a, b):
+    """minmod of the central difference (a + b)/2, 2a and 2b."""
+    return minmod(0.5 * (a + b), minmod(2.0 * a, 2.0 * b))
+
+
+def van_leer(a, b):
+    """(a |b| + |a| b) / (|a| + |b|), i.e. the harmonic mean 2ab / (a + b)
+    for ab > 0 and 0 otherwise."""
+    den = np.abs(a) + np.abs(b)
+    return np.where(den > 0.0, (a * np.abs(b) + np.abs(a) * b) / np.where(den > 0.0, den, 1.0), 0.0)
+
+
+LIMITERS = {"minmod": minmod, "superbee": superbee, "mc": monotonized_central, "van_leer": van_leer}
+
+
 def mirror_rows(N):
     """For each v_x row i the mirrored row N - i, or -1 for i = 0."""
     m = N - np.arange(N)
@@ -78,8 +104,9 @@ def ghosts(w, bc_left, bc_right, vx, hv2):
     return out
 
 
-def transport_step(w, dt, bc_left, bc_right, L):
-    """One step of eq. slopeLimiterStep of length dt, for every velocity."""
+def transport_step(w, dt, bc_left, bc_right, L, limiter="minmod"):
+    """One step of eq. slopeLimiterStep of length dt, for every velocity;
+    `limiter` names the slope limiter in place of minmod (LIMITERS)."""
     Nx, N = w.shape[0], w.shape[1]
     dx = 1.0 / Nx
     vx = (2.0 * L / N) * (np.arange(N) - N // 2)
@@ -87,7 +114,7 @@ def transport_step(w, dt, bc_left, bc_right, L):
     we = ghosts(w, bc_left, bc_right, vx, hv2)            # [Nx+4, N, N, 4]
     d = we[1:] - we[:-1]                                  # d[k] = we[k+1] - we[k]
     S = np.zeros_like(we)
-    S[1:-1] = minmod(d[1:], d[:-1])                       # S_k, k = 1..Nx+2
+    S[1:-1] = LIMITERS[limiter](d[1:], d[:-1])            # S_k, k = 1..Nx+2
     v = vx[None, :, None, None]
     av = np.abs(v)
     nu = dt * v / dx
