@@ -137,6 +137,30 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Scheme variants (Sec. 4: other slope limiters may replace minmod; the
+ * field term may be applied apart from the collision).
+ *   limiter: the slope S_j of eq. slopeLimiterStep from the one-sided
+ *     differences a = W_{j+1} - W_j, b = W_j - W_{j-1}, per Pauli component:
+ *     QB_LIMITER_MINMOD (eq. minmod, the default), QB_LIMITER_SUPERBEE (the
+ *     larger in magnitude of minmod(a, 2b) and minmod(2a, b)), QB_LIMITER_MC
+ *     (monotonized central, minmod((a + b)/2, minmod(2a, 2b))),
+ *     QB_LIMITER_VAN_LEER ((a|b| + |a|b) / (|a| + |b|), 0 when both vanish).
+ *   field: QB_FIELD_HEUN (the default: F = C + 2 (B x w).sigma inside the
+ *     Heun step) or QB_FIELD_ROTATION (the exact flow of the field term, a
+ *     rotation of the Bloch vector about B(x) by the angle 2|B| t, for dt/2
+ *     before and after a Heun step of C alone).
+ * Used by qb_transport_step and qb_step; the reverse mode (qb_transport_vjp, qb_step_trace, qb_adjoint_step) returns
+ * QB_ENOTSUP unless both are the defaults.  QB_EINVAL for other values.
+ * ------------------------------------------------------------------------- */
+#define QB_LIMITER_MINMOD 0
+#define QB_LIMITER_SUPERBEE 1
+#define QB_LIMITER_MC 2
+#define QB_LIMITER_VAN_LEER 3
+#define QB_FIELD_HEUN 0
+#define QB_FIELD_ROTATION 1
+qb_status qb_plan_set_scheme(qb_plan plan, int32_t limiter, int32_t field);
+
+/* ---------------------------------------------------------------------------
  * Term selection (Sec. 3.2 and the validation of Sec. 5.1, which measures
  * the conservative and the dissipative part separately): qb_collision and
  * qb_step assemble C = w_c C_c + w_d C_d with (w_c, w_d) = (1, 0) for

@@ -43,6 +43,7 @@ EXPORTS = (
     "qb_plan_set_adjoint_variant",
     "qb_plan_set_pairing",
     "qb_plan_set_terms",
+    "qb_plan_set_scheme",
     "qb_batch_create",
     "qb_batch_destroy",
     "qb_batch_bytes",
@@ -141,6 +142,8 @@ def _declare(lib):
     lib.qb_plan_set_pairing.argtypes = [vp, i32]
     lib.qb_plan_set_terms.argtypes = [vp, i32]
     lib.qb_plan_set_terms.restype = i32
+    lib.qb_plan_set_scheme.argtypes = [vp, i32, i32]
+    lib.qb_plan_set_scheme.restype = i32
     lib.qb_plan_set_pairing.restype = i32
     lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
     lib.qb_batch_create.restype = i32
@@ -454,6 +457,14 @@ class Plan:
         _check(self.lib.qb_plan_set_pairing(self.handle, 1 if paired else 0), "qb_plan_set_pairing")
 
     TERMS = {"conservative": 1, "dissipative": 2, "all": 3}
+    LIMITERS = {"minmod": 0, "superbee": 1, "mc": 2, "van_leer": 3}
+    FIELDS = {"heun": 0, "rotation": 1}
+
+    def set_scheme(self, limiter="minmod", field="heun"):
+        """qb_plan_set_scheme: slope limiter of the transport (LIMITERS) and
+        treatment of the field term (FIELDS)."""
+        _check(self.lib.qb_plan_set_scheme(self.handle, self.LIMITERS[limiter], self.FIELDS[field]),
+               "qb_plan_set_scheme")
 
     def set_terms(self, terms):
         """qb_plan_set_terms: assemble only C_c ('conservative'), only C_d

@@ -737,6 +737,28 @@ __global__ void k_heun(T* __restrict__ w, T* __restrict__ w1, const T* __restric
   }
 }
 
+// Exact flow of the field term over time tau: dw/dt = 2 B x w turns the
+// Bloch vector of cell x about B(x) by the angle 2 |B| tau (Rodrigues'
+// formula); w0 is unchanged.  State w[4][Nx][N][N].
+template <typename T>
+__global__ void k_rotate(T* __restrict__ w, const double* __restrict__ B, double tau, int Nx, int N) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = N * N;
+  if (idx >= Nx * per) return;
+  const int cell = idx / per;
+  const size_t cs = (size_t)Nx * per;
+  const double b1 = B[3 * cell], b2 = B[3 * cell + 1], b3 = B[3 * cell + 2];
+  const double nb = sqrt(b1 * b1 + b2 * b2 + b3 * b3);
+  if (!(nb > 0.0)) return;
+  const double th = 2.0 * nb * tau;
+  const T c = (T)cos(th), sn = (T)sin(th), k1 = (T)(b1 / nb), k2 = (T)(b2 / nb), k3 = (T)(b3 / nb);
+  const T v1 = w[cs + idx], v2 = w[2 * cs + idx], v3 = w[3 * cs + idx];
+  const T kv = (k1 * v1 + k2 * v2 + k3 * v3) * ((T)1 - c);
+  w[cs + idx] = v1 * c + (k2 * v3 - k3 * v2) * sn + k1 * kv;
+  w[2 * cs + idx] = v2 * c + (k3 * v1 - k1 * v3) * sn + k2 * kv;
+  w[3 * cs + idx] = v3 * c + (k1 * v2 - k2 * v1) * sn + k3 * kv;
+}
+
 // ------------------------------------------------------------------ transport
 struct BcDev {
   int kind;          // 0 periodic, 1 Dirichlet, 2 Maxwell
@@ -747,6 +769,29 @@ struct BcDev {
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
   return (a * b > (T)0) ? (fabs(a) <= fabs(b) ? a : b) : (T)0;
+}
+
+// Slope of a cell from its one-sided differences a = W_{j+1} - W_j and
+// b = W_j - W_{j-1} (Sec. 4: minmod, or another standard limiter):
+// 0 minmod; 1 superbee, the larger of minmod(a, 2b) and minmod(2a, b);
+// 2 monotonized central, minmod((a + b)/2, minmod(2a, 2b)); 3 van Leer,
+// (a |b| + |a| b) / (|a| + |b|).
+template <typename T>
+__device__ __forceinline__ T slope(int kind, T a, T b) {
+  switch (kind) {
+    case 1: {
+      const T s1 = minmod(a, (T)2 * b), s2 = minmod((T)2 * a, b);
+      return fabs(s1) >= fabs(s2) ? s1 : s2;
+    }
+    case 2:
+      return minmod((T)0.5 * (a + b), minmod((T)2 * a, (T)2 * b));
+    case 3: {
+      const T den = fabs(a) + fabs(b);
+      return den > (T)0 ? (a * fabs(b) + fabs(a) * b) / den : (T)0;
+    }
+    default:
+      return minmod(a, b);
+  }
 }
 
 // Maxwell: outgoing number flux Fbar = h^2 sum_out tr W_b |v_x| of the cell
@@ -812,7 +857,7 @@ __device__ __forceinline__ T ext_value(const T* __restrict__ w, const T* __restr
 template <typename T>
 __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T* __restrict__ bcw,
                             const double* __restrict__ flux, BcDev bl, BcDev br, T dt, int Nx, int N, T L,
-                            int Ntot) {
+                            int Ntot, int limiter) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int per = N * N;
   if (idx >= Nx * per) return;
@@ -833,9 +878,9 @@ __global__ void k_transport(const T* __restrict__ w, T* __restrict__ wn, const T
   const T av = fabs(vx);
   for (int mu = 0; mu < 4; ++mu) {
     const T* g = gval[mu];
-    const T Sm = minmod(g[2] - g[1], g[1] - g[0]);
-    const T S0 = minmod(g[3] - g[2], g[2] - g[1]);
-    const T Sp = minmod(g[4] - g[3], g[3] - g[2]);
+    const T Sm = slope(limiter, g[2] - g[1], g[1] - g[0]);
+    const T S0 = slope(limiter, g[3] - g[2], g[2] - g[1]);
+    const T Sp = slope(limiter, g[4] - g[3], g[3] - g[2]);
     const T upd = -vx * (g[3] - g[1]) + av * (g[3] - (T)2 * g[2] + g[1]) +
                   lim * (-vx * (Sp - Sm) + av * (Sp - (T)2 * S0 + Sm));
     wn[mu * cs + idx] = g[2] + dt / ((T)2 * dx) * upd;

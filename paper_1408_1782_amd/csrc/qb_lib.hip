@@ -409,7 +409,7 @@ void transport_seg(qb_plan_s* pl, const T* cur, T* tmp, double dt, const Segment
     hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur + off, g.flux, g.Nx, N, pl->prob.L, lm,
                        rm);
   hipLaunchKernelGGL((qb::k_transport<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur + off, tmp + off,
-                     (const T*)g.bcw, g.flux, g.bl, g.br, (T)dt, g.Nx, N, (T)pl->prob.L, ntot);
+                     (const T*)g.bcw, g.flux, g.bl, g.br, (T)dt, g.Nx, N, (T)pl->prob.L, ntot, pl->limiter);
 }
 
 template <typename T>
@@ -542,16 +542,30 @@ qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps
     T* rec = trace ? trace + (size_t)it * 3 * 4 * n : nullptr;
     if (rec && !hip_ok(hipMemcpyAsync(rec, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy")) return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
+    // field term: inside the Heun step, or its exact flow for dt/2 on
+    // either side of a collision-only Heun step
+    const bool rot = pl->field_mode == QB_FIELD_ROTATION && B;
+    const double* Bh = rot ? nullptr : B;
+    if (rot) {
+      const int rid = pl->begin(QB_K_HEUN, s);
+      hipLaunchKernelGGL((qb::k_rotate<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, B, 0.5 * dt, p.Nx, p.N);
+      pl->end(rid, s);
+    }
     if (!collision_any<T>(pl, cur, c, p.Nx, s)) return QB_EHIP;
     int id = pl->begin(QB_K_HEUN, s);
-    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 1);
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, Bh, (T)dt, p.Nx, p.N, 1);
     pl->end(id, s);
     if (rec && !hip_ok(hipMemcpyAsync(rec + 4 * n, w1, sb, hipMemcpyDeviceToDevice, s), "trace copy"))
       return QB_EHIP;
     if (!collision_any<T>(pl, w1, c, p.Nx, s)) return QB_EHIP;
     id = pl->begin(QB_K_HEUN, s);
-    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, B, (T)dt, p.Nx, p.N, 2);
+    hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, Bh, (T)dt, p.Nx, p.N, 2);
     pl->end(id, s);
+    if (rot) {
+      const int rid = pl->begin(QB_K_HEUN, s);
+      hipLaunchKernelGGL((qb::k_rotate<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, B, 0.5 * dt, p.Nx, p.N);
+      pl->end(rid, s);
+    }
     if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
     if (rec && !hip_ok(hipMemcpyAsync(rec + 8 * n, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy"))
       return QB_EHIP;
@@ -1017,6 +1031,7 @@ size_t qb_trace_bytes(qb_plan plan) {
 qb_status qb_step_trace(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, void* trace,
                         void* stream) {
   if (!plan || !W || !trace || nsteps < 0) return QB_EINVAL;
+  if (plan->limiter != QB_LIMITER_MINMOD || plan->field_mode != QB_FIELD_HEUN) return QB_ENOTSUP;
   qb_status st = check_cfl(plan, 0.5 * dt);
   if (st != QB_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1036,6 +1051,7 @@ qb_status qb_collision_vjp(qb_plan plan, const void* W, const void* lam, void* G
 qb_status qb_transport_vjp(qb_plan plan, const void* W, double dt, const void* lam, void* G, void* stream) {
   if (!plan || !W || !lam || !G) return QB_EINVAL;
   if (!plan->adjoint) return QB_EWORKSPACE;
+  if (plan->limiter != QB_LIMITER_MINMOD) return QB_ENOTSUP;
   qb_status st = check_cfl(plan, dt);
   if (st != QB_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1048,6 +1064,7 @@ qb_status qb_adjoint_step(qb_plan plan, const void* W, const void* record, const
   if (!plan || (!W && !record) || !lam_next || !lam) return QB_EINVAL;
   if (!plan->adjoint) return QB_EWORKSPACE;
   if (plan->term_sel != QB_TERMS_ALL) return QB_ENOTSUP;
+  if (plan->limiter != QB_LIMITER_MINMOD || plan->field_mode != QB_FIELD_HEUN) return QB_ENOTSUP;
   qb_status st = check_cfl(plan, 0.5 * dt);
   if (st != QB_OK) return st;
   hipStream_t s = (hipStream_t)stream;
@@ -1136,6 +1153,15 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E) {
   if (std::find(c.begin(), c.end(), (int)E) == c.end()) return QB_ENOTSUP;
   const bool ok = plan->prob.precision == QB_F64 ? select_tile<double>(plan, E) : select_tile<float>(plan, E);
   return ok ? QB_OK : QB_EHIP;
+}
+
+qb_status qb_plan_set_scheme(qb_plan plan, int32_t limiter, int32_t field) {
+  if (!plan || limiter < QB_LIMITER_MINMOD || limiter > QB_LIMITER_VAN_LEER || field < QB_FIELD_HEUN ||
+      field > QB_FIELD_ROTATION)
+    return QB_EINVAL;
+  plan->limiter = limiter;
+  plan->field_mode = field;
+  return QB_OK;
 }
 
 qb_status qb_plan_set_terms(qb_plan plan, int32_t terms) {

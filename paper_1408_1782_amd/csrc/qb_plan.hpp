@@ -25,6 +25,8 @@ struct qb_plan_s {
   bool i3_pair = true;  // I_3 kernel pairs the Gauss-Legendre nodes (tuned; default per tile)
   int vjp_variant = 0;  // I_3 adjoint: 0 accumulators in memory, 1 Y in registers, 2 Y and w_bar (tuned)
   int term_sel = 3;     // collision terms assembled: 1 C_c, 2 C_d, 3 both
+  int limiter = 0;      // transport slope limiter: 0 minmod, 1 superbee, 2 MC, 3 van Leer
+  int field_mode = 0;   // field term: 0 inside the Heun step, 1 exact rotation split around it
   size_t bytes = 0;
   std::vector<void*> allocs;
   // quadrature tables in the FFT engine's element order, one set per tile

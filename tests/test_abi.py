@@ -79,3 +79,4 @@ def test_null_arguments_rejected():
     assert lib.qb_trace_bytes(None) == 0
     assert lib.qb_diagnostics(None, None, None, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_plan_set_terms(None, 3) == _lib.QB_EINVAL
+    assert lib.qb_plan_set_scheme(None, 0, 0) == _lib.QB_EINVAL
