@@ -426,6 +426,17 @@ struct I3Regs {
     return PR && !sreg<PR>() && P == 128 && sizeof(T) == 4 &&
            (LDS_SCALARS + P * P) * (int)sizeof(T) <= 160 * 1024;
   }
+  // At P = 64 with E = 16 (256 threads) the register plan leaves two
+  // workgroups per compute unit, each with half of the 160 KB of LDS: the
+  // output accumulators that fit beside the transpose buffer stay in LDS for
+  // the whole node loop (3 in float32, 1 in float64) instead of going
+  // through memory at every node.
+  template <bool PR, int LDS_SCALARS>
+  static constexpr int lds_acc() {
+    if (!PR || P != 64 || NT != 256) return 0;
+    const int k = (80 * 1024 - LDS_SCALARS * (int)sizeof(T)) / (P * P * (int)sizeof(T));
+    return k < 0 ? 0 : (k > 4 ? 4 : k);
+  }
 };
 
 template <typename T>
@@ -448,6 +459,11 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   constexpr bool PF = I3Regs<T, P, E>::template lds_field<PAIR, K::LDS>();
   __shared__ T smem[K::LDS];
   __shared__ T pf[PF ? K::FSZ : 1];
+  // KRES accumulator fields resident in LDS; each thread touches only its
+  // own elements, so no barrier guards them
+  constexpr int KRES = I3Regs<T, P, E>::template lds_acc<PAIR, K::LDS>();
+  __shared__ T acc[KRES > 0 ? KRES * K::FSZ : 1];
+  const unsigned tid = threadIdx.x;
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
   const int task = xcd_task(blockIdx.x, gridDim.x);
@@ -549,6 +565,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         const T e0 = m0 == 0 ? wgt : -wgt;
         const T ew = nu == 0 ? wgt : -wgt;  // c eta_nu
         const unsigned pt = PF ? lds_fetch_wait() : 0u;
+        const bool res = KRES > 0 && nu < KRES;
+        T* const al = acc + (KRES > 0 && res ? nu * K::FSZ : 0) + tid;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
@@ -565,8 +583,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           }
           const unsigned off = (nu * K::FSZ + o) * S;
           T v = e0 * sa * zr[n] - wgt * sb * zi[n];
-          if (!first) v += PF ? pf[PF ? o + pt : 0] : bld<T>(ro, vo, off);
-          bst<T>(ro, v, vo, off);
+          if (KRES > 0 && res) {
+            if (!first) v += al[KRES > 0 ? o : 0];
+            al[KRES > 0 ? o : 0] = v;
+          } else {
+            if (!first) v += PF ? pf[PF ? o + pt : 0] : bld<T>(ro, vo, off);
+            bst<T>(ro, v, vo, off);
+          }
           if constexpr (PAIR) {
             if (paired) {
               const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
@@ -611,6 +634,14 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           bst<T>(rp, (T)0, vo, (fi + k * K::NT) * S);
         }
       }
+    }
+  }
+  // the LDS-resident accumulators go to memory once
+  if constexpr (KRES > 0) {
+#pragma unroll 1
+    for (int f = 0; f < KRES; ++f) {
+#pragma unroll
+      for (int n = 0; n < E; ++n) bst<T>(ro, acc[f * K::FSZ + n * K::NT + tid], vo, (f * K::FSZ + n * K::NT) * S);
     }
   }
 }
