@@ -123,7 +123,8 @@ def run_gpu(wl, precision, steps, warmup):
     m = mom.cpu().numpy()
     tot0, tot1 = m[0].sum(0), m[-1].sum(0)
     plan.close()
-    return t1 - t0, kern, tot0, tot1, cfg
+    final = {"W": _pauli_np(W.cpu().numpy().astype(np.complex128)), "moments": m[-1]}
+    return t1 - t0, kern, tot0, tot1, cfg, final
 
 
 def run_adjoint(steps, every):
@@ -382,7 +383,7 @@ def main():
         copy_calibration()
     wl = workloads.config(3, Nx=args.nx)
     log(f"workload {wl.name}: Nx={wl.Nx} N={wl.N} J={wl.J} M={wl.M} dt={wl.dt}")
-    t32, k32, a32, b32, cfg32 = run_gpu(wl, "f32", args.steps, args.warmup)
+    t32, k32, a32, b32, cfg32, fin32 = run_gpu(wl, "f32", args.steps, args.warmup)
     out = {
         "metric": METRIC,
         "value": wl.Nx * args.steps / t32,
@@ -407,8 +408,12 @@ def main():
         paired = cfg["paired_nodes"]
         ach = i3_flops(wl.Nx, wl.N, wl.J, wl.M, paired) / avg_s / 1e12
         traffic = measured_traffic(precision, cfg["tile"]) if wl.Nx == 256 else None
+        # counter-measured bytes moved between L2 and the fabric (MALL or HBM)
+        # per launch over the launch time, against the 8 TB/s HBM peak
+        hbm = None if traffic is None else {"GB/s": traffic / avg_s / 1e9, "peak": 8000.0,
+                                            "frac": traffic / avg_s / 8e12}
         return {"kernel": "k_i3", "bound": "alu", "achieved": ach, "peak": PEAK[precision],
-                "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": traffic,
+                "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": traffic, "hbm_measured": hbm,
                 "avg_launch_ms": ms / max(n, 1), "launches": n, "tile": cfg["tile"],
                 "paired_nodes": paired,
                 "transforms_per_cell": i3_transforms(wl.J, wl.M, paired)}
@@ -418,11 +423,20 @@ def main():
     drift = lambda a, b: {"density": float((b[0] - a[0]) / a[0]), "energy": float((b[6] - a[6]) / a[6])}
     out["moment_drift_f32"] = drift(a32, b32)
     if not args.no_f64:
-        t64, k64, a64, b64, cfg64 = run_gpu(wl, "f64", args.steps, args.warmup)
+        t64, k64, a64, b64, cfg64, fin64 = run_gpu(wl, "f64", args.steps, args.warmup)
         out["value_f64"] = wl.Nx * args.steps / t64
         out["ms_per_step_f64"] = 1e3 * t64 / args.steps
         out["roofline_f64"] = roof(k64, "f64", cfg64)
         out["moment_drift_f64"] = drift(a64, b64)
+        # the float32 bulk path against float64 on the same input and steps
+        # (warmup included): normwise relative difference per result
+        nrm = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+        out["fp32_vs_fp64"] = {
+            "steps": args.steps + args.warmup,
+            "state": nrm(fin32["W"], fin64["W"]),
+            "moments": {name: nrm(fin32["moments"][:, k], fin64["moments"][:, k])
+                        for k, name in enumerate(("rho0", "rho1", "rho2", "rho3", "p_x", "p_y", "energy"))},
+        }
     out["adjoint_forward_ratio"] = None
     if args.adj_steps > 0:
         adj = run_adjoint(args.adj_steps, args.adj_every)
