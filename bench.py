@@ -91,6 +91,17 @@ def i3_flops(ncells, N, J, M, paired):
 
 
 
+def measure_ceilings():
+    """Sustained vector FMA rates and device copy bandwidth of this GPU
+    (qb_probe_fma / qb_probe_copy), beside the datasheet peaks."""
+    from paper_1408_1782_amd import _lib
+
+    c = {"fma_f32_TFLOPs": _lib.probe_fma("f32", 4096), "fma_f64_TFLOPs": _lib.probe_fma("f64", 4096),
+         "copy_GBps": _lib.probe_copy(1024)}
+    log(f"measured ceilings: {c}")
+    return c
+
+
 def run_gpu(wl, precision, steps, warmup):
     import torch
     import paper_1408_1782_amd as qb
@@ -381,6 +392,7 @@ def main():
 
     if args.calibrate_copy:
         copy_calibration()
+    ceil = measure_ceilings()
     wl = workloads.config(3, Nx=args.nx)
     log(f"workload {wl.name}: Nx={wl.Nx} N={wl.N} J={wl.J} M={wl.M} dt={wl.dt}")
     t32, k32, a32, b32, cfg32, fin32 = run_gpu(wl, "f32", args.steps, args.warmup)
@@ -411,13 +423,17 @@ def main():
         # counter-measured bytes moved between L2 and the fabric (MALL or HBM)
         # per launch over the launch time, against the 8 TB/s HBM peak
         hbm = None if traffic is None else {"GB/s": traffic / avg_s / 1e9, "peak": 8000.0,
-                                            "frac": traffic / avg_s / 8e12}
+                                            "frac": traffic / avg_s / 8e12,
+                                            "frac_of_measured_copy": traffic / avg_s / 1e9 / ceil["copy_GBps"]}
+        fma = ceil["fma_f32_TFLOPs" if precision == "f32" else "fma_f64_TFLOPs"]
         return {"kernel": "k_i3", "bound": "alu", "achieved": ach, "peak": PEAK[precision],
                 "unit": "TFLOP/s", "frac": ach / PEAK[precision], "traffic": traffic, "hbm_measured": hbm,
+                "measured_fma_peak": fma, "frac_of_measured_fma": ach / fma,
                 "avg_launch_ms": ms / max(n, 1), "launches": n, "tile": cfg["tile"],
                 "paired_nodes": paired,
                 "transforms_per_cell": i3_transforms(wl.J, wl.M, paired)}
 
+    out["ceilings"] = ceil
     out["roofline"] = roof(k32, "f32", cfg32)
     out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in k32.items()}
     drift = lambda a, b: {"density": float((b[0] - a[0]) / a[0]), "energy": float((b[6] - a[6]) / a[6])}

@@ -175,6 +175,26 @@ qb_status qb_plan_set_scheme(qb_plan plan, int32_t limiter, int32_t field);
 qb_status qb_plan_set_terms(qb_plan plan, int32_t terms);
 
 /* ---------------------------------------------------------------------------
+ * Ceiling probes (measurement instrumentation, not part of the solver):
+ * the rates this GPU sustains, for reading the kernels' roofline fractions
+ * against measured ceilings beside the datasheet figures.  Both calls block
+ * until their launches on `stream` finish (one warm-up launch, then timed
+ * repetitions between two HIP events).
+ *   qb_probe_fma: vector fused multiply-add throughput in TFLOP/s of the
+ *     plan precisions (QB_F32: float, unpacked, as the library is compiled;
+ *     QB_F64: double): 4096 x 256 threads, 8 independent chains of 8 x iters
+ *     FMAs each.  scratch: device buffer of at least 32768 bytes (written
+ *     only if a result takes a value it never takes).
+ *   qb_probe_copy: device-to-device copy bandwidth in GB/s (bytes read plus
+ *     bytes written per second) of `reps` 16-byte-vector copies of `bytes`
+ *     (a multiple of 16) from src to dst (device buffers, not overlapping).
+ * QB_EINVAL for null pointers or sizes out of range, QB_EHIP on a failed
+ * HIP call.
+ * ------------------------------------------------------------------------- */
+qb_status qb_probe_fma(int32_t precision, int32_t iters, void* scratch, double* tflops, void* stream);
+qb_status qb_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps, double* gbps, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Diagnostics of a state (Sec. 2 and Sec. 5), float64 whatever the plan's
  * precision, one row of QB_DIAG_FIELDS values per cell:
  *   0  local entropy S = -h^2 sum_v tr[W log W + W~ log W~], W~ = 1 - W

@@ -31,6 +31,8 @@ EXPORTS = (
     "qb_step",
     "qb_moments",
     "qb_diagnostics",
+    "qb_probe_fma",
+    "qb_probe_copy",
     "qb_plan_enable_adjoint",
     "qb_collision_vjp",
     "qb_transport_vjp",
@@ -119,6 +121,10 @@ def _declare(lib):
     lib.qb_moments.restype = i32
     lib.qb_diagnostics.argtypes = [vp, vp, vp, ctypes.POINTER(_FD), vp, vp]
     lib.qb_diagnostics.restype = i32
+    lib.qb_probe_fma.argtypes = [i32, i32, vp, ctypes.POINTER(dbl), vp]
+    lib.qb_probe_fma.restype = i32
+    lib.qb_probe_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(dbl), vp]
+    lib.qb_probe_copy.restype = i32
     lib.qb_plan_enable_adjoint.argtypes = [vp]
     lib.qb_plan_enable_adjoint.restype = i32
     lib.qb_collision_vjp.argtypes = [vp, vp, vp, vp, i32, vp]
@@ -580,3 +586,29 @@ class Batch:
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.qb_batch_destroy(self.handle)
             self.handle = ctypes.c_void_p()
+
+
+def probe_fma(precision="f32", iters=4096):
+    """qb_probe_fma: sustained vector FMA rate in TFLOP/s on the current GPU."""
+    import torch
+
+    lib = load()
+    scratch = torch.empty(32768, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_double()
+    _check(lib.qb_probe_fma(QB_F64 if precision == "f64" else QB_F32, int(iters), _ptr(scratch), ctypes.byref(out),
+                            _stream()), "qb_probe_fma")
+    return out.value
+
+
+def probe_copy(mib=1024, reps=5):
+    """qb_probe_copy: device copy bandwidth in GB/s (read + write) over two
+    buffers of `mib` MiB."""
+    import torch
+
+    lib = load()
+    n = int(mib) << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    out = ctypes.c_double()
+    _check(lib.qb_probe_copy(_ptr(src), _ptr(dst), n, int(reps), ctypes.byref(out), _stream()), "qb_probe_copy")
+    return out.value

@@ -80,3 +80,5 @@ def test_null_arguments_rejected():
     assert lib.qb_diagnostics(None, None, None, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_plan_set_terms(None, 3) == _lib.QB_EINVAL
     assert lib.qb_plan_set_scheme(None, 0, 0) == _lib.QB_EINVAL
+    assert lib.qb_probe_fma(0, 1, None, None, None) == _lib.QB_EINVAL
+    assert lib.qb_probe_copy(None, None, 16, 1, None, None) == _lib.QB_EINVAL
