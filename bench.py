@@ -24,7 +24,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "cells*steps/s at 64x64 momentum grid (FP64 vs FP32); adjoint/forward time ratio"
-PEAK = {"f32": 157.3, "f64": 78.6}   # TFLOP/s, MI355X vector (fp32 figure assumes packed math)
+PEAK = {"f32": 157.3, "f64": 78.6}   # TFLOP/s, MI355X datasheet vector peaks
 
 
 def log(*a):
