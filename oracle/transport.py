@@ -127,3 +127,42 @@ def transport_step(w, dt, bc_left, bc_right, L, limiter="minmod"):
         + lim * (-v * (Sp - Sm) + av * (Sp - 2.0 * S0 + Sm))
     )
     return W0 + (dt / (2.0 * dx)) * upd
+
+
+def face_fluxes(w, dt, bc_left, bc_right, L, limiter="minmod"):
+    """The step of eq. slopeLimiterStep in flux form,
+    W_j <- W_j - (dt/dx) (F_{j+1/2} - F_{j-1/2}), with
+    F_{j+1/2} = (v (W_j + W_{j+1}) - |v| (W_{j+1} - W_j)) / 2
+              + l (v (S_j + S_{j+1}) - |v| (S_{j+1} - S_j)) / 2,
+    l = (sgn nu - nu) / 2: the fluxes through the Nx + 1 faces j + 1/2,
+    j = -1 .. Nx - 1 (the first and last are the walls), [Nx + 1, N, N, 4]."""
+    Nx, N = w.shape[0], w.shape[1]
+    dx = 1.0 / Nx
+    vx = (2.0 * L / N) * (np.arange(N) - N // 2)
+    hv2 = (2.0 * L / N) ** 2
+    we = ghosts(w, bc_left, bc_right, vx, hv2)
+    d = we[1:] - we[:-1]
+    S = np.zeros_like(we)
+    S[1:-1] = LIMITERS[limiter](d[1:], d[:-1])
+    v = vx[None, :, None, None]
+    av = np.abs(v)
+    lim = 0.5 * (np.sign(dt * v / dx) - dt * v / dx)
+    a, b = we[1:Nx + 2], we[2:Nx + 3]
+    Sa, Sb = S[1:Nx + 2], S[2:Nx + 3]
+    return 0.5 * (v * (a + b) - av * (b - a)) + 0.5 * lim * (v * (Sa + Sb) - av * (Sb - Sa))
+
+
+def wall_inflow_moments(w, dt, bc_left, bc_right, L, limiter="minmod"):
+    """Net inflow through the two walls during one step of length dt, as the
+    change it makes to the per-cell moments of step.moments summed over the
+    cells: (dt/dx) h_v^2 sum_v phi(v) (F_{1/2} - F_{Nx+1/2}) with phi the
+    functionals (rho_0..3, p_x, p_y, energy); returns [7]."""
+    Nx, N = w.shape[0], w.shape[1]
+    F = face_fluxes(w, dt, bc_left, bc_right, L, limiter)
+    net = F[0] - F[-1]
+    h = 2.0 * L / N
+    vx, vy = np.meshgrid(h * (np.arange(N) - N // 2), h * (np.arange(N) - N // 2), indexing="ij")
+    tr = 2.0 * net[..., 0]
+    out = np.concatenate([net.sum(axis=(0, 1)),
+                          [(vx * tr).sum(), (vy * tr).sum(), (0.5 * (vx**2 + vy**2) * tr).sum()]])
+    return dt * Nx * h * h * out

@@ -12,7 +12,10 @@ against textbook forms and properties that do not use the variant's code:
 * the field flow keeps w0 and |w| and is a one-parameter group whose
   generator is the field term 2 B x w; for B along e_3 it is the closed-form
   rotation;
-* the two splittings of the field agree to second order in dt.
+* the two splittings of the field agree to second order in dt;
+* the flux form of the limited step (face fluxes written out from
+  eq. slopeLimiterStep) gives back the step cell by cell, so the change of
+  the total moments over a transport step is exactly the wall inflow.
 """
 import numpy as np
 import pytest
@@ -128,3 +131,33 @@ def test_field_splittings_agree_to_second_order():
         b = ostep.step(w0, B, dt, L, 7.5, J, M, per, per, t, field="rotation")
         diff.append(np.abs(a - b).max())
     assert diff[0] / diff[1] > 6.0, diff
+
+
+@pytest.mark.parametrize("kind", ["periodic", "dirichlet", "maxwell"])
+@pytest.mark.parametrize("name", ["minmod", "van_leer"])
+def test_flux_form_reproduces_the_step(kind, name):
+    """The face fluxes written out from eq. slopeLimiterStep give back the
+    step cell by cell, so the change of the cell-summed moments is exactly
+    the wall inflow."""
+    rng = np.random.default_rng(8)
+    Nx, N = 10, 8
+    w = pauli.to_pauli(wl.config(3, Nx=Nx, N=N).W0) + 0.01 * rng.standard_normal((Nx, N, N, 4))
+    v = (2 * L / N) * (np.arange(N) - N // 2)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    from oracle.fermi_dirac import fd_matrix
+    st = lambda ikT: pauli.to_pauli(fd_matrix(vx, vy, ikT, 0.3, -0.2))
+    if kind == "periodic":
+        bl = br = {"kind": "periodic"}
+    elif kind == "dirichlet":
+        bl, br = {"kind": "dirichlet", "state": st(0.8)}, {"kind": "dirichlet", "state": st(2.0)}
+    else:
+        bl, br = {"kind": "dirichlet", "state": st(0.8)}, {"kind": "maxwell", "state": st(2.0), "alpha": 0.5}
+    dt = 0.7 / (L * Nx)
+    w1 = tp.transport_step(w, dt, bl, br, L, name)
+    F = tp.face_fluxes(w, dt, bl, br, L, name)
+    assert np.allclose(w1, w - dt * Nx * (F[1:] - F[:-1]), rtol=0, atol=1e-14 * np.abs(w).max())
+    dm = ostep.moments(w1, L).sum(0) - ostep.moments(w, L).sum(0)
+    inflow = tp.wall_inflow_moments(w, dt, bl, br, L, name)
+    assert np.allclose(dm, inflow, rtol=0, atol=1e-12 * np.abs(ostep.moments(w, L)).sum(0).max())
+    if kind == "periodic":
+        assert np.abs(inflow).max() < 1e-13
