@@ -123,9 +123,10 @@ def run_gpu(wl, precision, steps, warmup):
     plan.profile(True)
     for k in qb._lib.KERNELS:
         plan.profile_read(k)     # discard anything recorded before
+    inflow = torch.zeros((steps, 7), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan.step(W, B, wl.dt, steps, mom)
+    plan.step(W, B, wl.dt, steps, mom, inflow)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"[{precision}] {steps} step(s) in {t1 - t0:.3f} s")
@@ -134,7 +135,8 @@ def run_gpu(wl, precision, steps, warmup):
     m = mom.cpu().numpy()
     tot0, tot1 = m[0].sum(0), m[-1].sum(0)
     plan.close()
-    final = {"W": _pauli_np(W.cpu().numpy().astype(np.complex128)), "moments": m[-1]}
+    final = {"W": _pauli_np(W.cpu().numpy().astype(np.complex128)), "moments": m[-1],
+             "inflow": inflow.cpu().numpy().sum(axis=0)}
     return t1 - t0, kern, tot0, tot1, cfg, final
 
 
@@ -437,13 +439,24 @@ def main():
     out["roofline"] = roof(k32, "f32", cfg32)
     out["kernel_ms_per_step"] = {k: v[0] / args.steps for k, v in k32.items()}
     drift = lambda a, b: {"density": float((b[0] - a[0]) / a[0]), "energy": float((b[6] - a[6]) / a[6])}
+
+    def budget(a, b, fin):
+        # total change minus the inflow through the walls, relative to the
+        # initial totals: what the collision and field sub-steps changed
+        inf = fin["inflow"]
+        return {"density_inflow": float(inf[0] / a[0]), "energy_inflow": float(inf[6] / a[6]),
+                "density_residual": float((b[0] - a[0] - inf[0]) / a[0]),
+                "energy_residual": float((b[6] - a[6] - inf[6]) / a[6])}
+
     out["moment_drift_f32"] = drift(a32, b32)
+    out["conservation_budget_f32"] = budget(a32, b32, fin32)
     if not args.no_f64:
         t64, k64, a64, b64, cfg64, fin64 = run_gpu(wl, "f64", args.steps, args.warmup)
         out["value_f64"] = wl.Nx * args.steps / t64
         out["ms_per_step_f64"] = 1e3 * t64 / args.steps
         out["roofline_f64"] = roof(k64, "f64", cfg64)
         out["moment_drift_f64"] = drift(a64, b64)
+        out["conservation_budget_f64"] = budget(a64, b64, fin64)
         # the float32 bulk path against float64 on the same input and steps
         # (warmup included): normwise relative difference per result
         nrm = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())

@@ -133,6 +133,19 @@ qb_status qb_transport_step(qb_plan plan, void* W, double dt, void* stream);
 qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, double* moments,
                   void* stream);
 
+/* qb_step that also returns the moments of the net inflow through the two
+ * walls during every step (both transport half-steps), float64 device
+ * array inflow[nsteps][7] in the units of the per-cell moments summed over
+ * the cells: with the scheme written in flux form, W_j <- W_j - (dt/dx)
+ * (F_{j+1/2} - F_{j-1/2}) (eq. slopeLimiterStep), the transport changes the
+ * cell-summed moments by exactly (dt/dx) h^2 sum_v phi(v) (F_{1/2} -
+ * F_{Nx+1/2}), so total moments minus accumulated inflow isolate what the
+ * collision and field sub-steps change (the conservation budget of Sec. 2
+ * on a bounded slab; zero inflow for periodic walls).  Other arguments and
+ * errors as qb_step (QB_EINVAL also for a null inflow). */
+qb_status qb_step_fluxes(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, double* moments,
+                         double* inflow, void* stream);
+
 /* float64 moments [Nx][7] of W ([Nx][N][N][2][2] complex). */
 qb_status qb_moments(qb_plan plan, const void* W, double* moments, void* stream);
 

@@ -29,6 +29,7 @@ EXPORTS = (
     "qb_collision",
     "qb_transport_step",
     "qb_step",
+    "qb_step_fluxes",
     "qb_moments",
     "qb_diagnostics",
     "qb_probe_fma",
@@ -116,6 +117,8 @@ def _declare(lib):
     lib.qb_transport_step.argtypes = [vp, vp, dbl, vp]
     lib.qb_transport_step.restype = i32
     lib.qb_step.argtypes = [vp, vp, vp, dbl, i32, vp, vp]
+    lib.qb_step_fluxes.argtypes = [vp, vp, vp, dbl, i32, vp, vp, vp]
+    lib.qb_step_fluxes.restype = i32
     lib.qb_step.restype = i32
     lib.qb_moments.argtypes = [vp, vp, vp, vp]
     lib.qb_moments.restype = i32
@@ -302,9 +305,11 @@ class Plan:
         _check(self.lib.qb_transport_step(self.handle, _ptr(W), float(dt), _stream()), "qb_transport_step")
         return W
 
-    def step(self, W, B=None, dt=1e-3, nsteps=1, moments=None):
+    def step(self, W, B=None, dt=1e-3, nsteps=1, moments=None, inflow=None):
         """qb_step: nsteps splitting steps in place; B float64 [Nx, 3] or None;
-        moments float64 [nsteps + 1, Nx, 7] or None."""
+        moments float64 [nsteps + 1, Nx, 7] or None; with inflow (float64
+        [nsteps, 7]) qb_step_fluxes, which also returns the moments of the
+        net inflow through the walls during each step."""
         import torch
 
         self._check_state(W)
@@ -319,6 +324,13 @@ class Plan:
             if moments.dtype != torch.float64 or tuple(moments.shape) != (nsteps + 1, p.Nx, 7):
                 raise ValueError("moments must be CUDA float64 [nsteps + 1, Nx, 7]")
             mp = _ptr(moments)
+        if inflow is not None:
+            if inflow.dtype != torch.float64 or not inflow.is_cuda or tuple(inflow.shape) != (nsteps, 7) \
+                    or not inflow.is_contiguous():
+                raise ValueError("inflow must be a contiguous CUDA float64 tensor [nsteps, 7]")
+            _check(self.lib.qb_step_fluxes(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _ptr(inflow),
+                                           _stream()), "qb_step_fluxes")
+            return W
         _check(self.lib.qb_step(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _stream()), "qb_step")
         return W
 

@@ -412,6 +412,82 @@ void transport_seg(qb_plan_s* pl, const T* cur, T* tmp, double dt, const Segment
                      (const T*)g.bcw, g.flux, g.bl, g.br, (T)dt, g.Nx, N, (T)pl->prob.L, ntot, pl->limiter);
 }
 
+// Net inflow through the two walls during one transport step of length dt,
+// from the flux form of eq. slopeLimiterStep, W_j <- W_j - (dt/dx)
+// (F_{j+1/2} - F_{j-1/2}) with
+//   F_{j+1/2} = (v (W_j + W_{j+1}) - |v| (W_{j+1} - W_j)) / 2
+//             + l (v (S_j + S_{j+1}) - |v| (S_{j+1} - S_j)) / 2,
+// l = (sgn nu - nu) / 2, in the units of the cell-summed moments:
+// (dt/dx) h^2 sum_v phi(v) (F_{1/2} - F_{Nx+1/2}) for phi = (rho_0..3,
+// v_x tr, v_y tr, |v|^2/2 tr); written to out[0..6], or added to it.
+// One workgroup of 256 threads.
+template <typename T>
+__global__ __launch_bounds__(256) void k_wall_inflow(const T* __restrict__ w, const T* __restrict__ bcw,
+                                                     const double* __restrict__ flux, qb::BcDev bl, qb::BcDev br, T dt,
+                                                     int Nx, int N, T L, int Ntot, int limiter,
+                                                     double* __restrict__ out, int accumulate) {
+  const int per = N * N;
+  const size_t cs = (size_t)Ntot * per;
+  const T h = (T)2 * L / (T)N;
+  const T dx = (T)1 / (T)Nx;
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int e = threadIdx.x; e < per; e += blockDim.x) {
+    const int i = e / N;
+    const T vx = h * (T)(i - N / 2), vy = h * (T)(e % N - N / 2);
+    const T nu = dt * vx / dx;
+    const T sg = vx > (T)0 ? (T)1 : (vx < (T)0 ? (T)-1 : (T)0);
+    const T lim = (T)0.5 * (sg - nu);
+    const T av = fabs(vx);
+    for (int mu = 0; mu < 4; ++mu) {
+      T F[2];
+      for (int side = 0; side < 2; ++side) {
+        // cells c0 .. c0 + 3 around the face between c0 + 1 and c0 + 2
+        const int c0 = side == 0 ? -2 : Nx - 2;
+        T g[4];
+        for (int k = 0; k < 4; ++k) g[k] = qb::ext_value(w, bcw, flux, bl, br, mu, c0 + k, e, i, vx, Nx, N, cs);
+        const T Sa = qb::slope(limiter, g[2] - g[1], g[1] - g[0]);
+        const T Sb = qb::slope(limiter, g[3] - g[2], g[2] - g[1]);
+        F[side] = (T)0.5 * (vx * (g[1] + g[2]) - av * (g[2] - g[1])) +
+                  (T)0.5 * lim * (vx * (Sa + Sb) - av * (Sb - Sa));
+      }
+      const double net = (double)F[0] - (double)F[1];
+      acc[mu] += net;
+      if (mu == 0) {
+        acc[4] += (double)vx * 2.0 * net;
+        acc[5] += (double)vy * 2.0 * net;
+        acc[6] += 0.5 * ((double)vx * vx + (double)vy * vy) * 2.0 * net;
+      }
+    }
+  }
+  __shared__ double red[7][256];
+  for (int k = 0; k < 7; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o)
+      for (int k = 0; k < 7; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) {
+    const double sc = (double)dt * Nx * (double)h * (double)h;
+    const double v = sc * red[threadIdx.x][0];
+    out[threadIdx.x] = accumulate ? out[threadIdx.x] + v : v;
+  }
+}
+
+// out[0..6] (= or +=) the moments of the net inflow through the walls
+// during the transport step of length dt that is about to run on cur
+template <typename T>
+bool wall_inflow(qb_plan_s* pl, const T* cur, double dt, double* out, bool accumulate, hipStream_t s) {
+  const Segment g = whole(pl);
+  const int N = pl->prob.N;
+  if (g.left_maxwell || g.right_maxwell)
+    hipLaunchKernelGGL((qb::k_maxwell_flux<T>), dim3(2), dim3(256), 0, s, cur, g.flux, g.Nx, N, pl->prob.L,
+                       (int)g.left_maxwell, (int)g.right_maxwell);
+  hipLaunchKernelGGL((k_wall_inflow<T>), dim3(1), dim3(256), 0, s, cur, (const T*)g.bcw, g.flux, g.bl, g.br,
+                     (T)dt, g.Nx, N, (T)pl->prob.L, g.Nx, pl->limiter, out, accumulate ? 1 : 0);
+  return hip_ok(hipGetLastError(), "wall inflow launch");
+}
+
 template <typename T>
 bool transport(qb_plan_s* pl, T*& cur, T*& tmp, double dt, hipStream_t s) {
   const int id = pl->begin(QB_K_TRANSPORT, s);
@@ -526,7 +602,7 @@ qb_status do_collision(qb_plan_s* pl, const void* W, void* C, int ncells, hipStr
 
 template <typename T>
 qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps, double* mom, T* trace,
-                  hipStream_t s) {
+                  hipStream_t s, double* inflow = nullptr) {
   const qb_problem& p = pl->prob;
   T* cur = (T*)pl->st0;
   T* tmp = (T*)pl->st2;
@@ -541,6 +617,7 @@ qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps
     // trace record of this step: [step input, Heun stage 1, Heun output]
     T* rec = trace ? trace + (size_t)it * 3 * 4 * n : nullptr;
     if (rec && !hip_ok(hipMemcpyAsync(rec, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy")) return QB_EHIP;
+    if (inflow && !wall_inflow<T>(pl, cur, 0.5 * dt, inflow + (size_t)it * 7, false, s)) return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     // field term: inside the Heun step, or its exact flow for dt/2 on
     // either side of a collision-only Heun step
@@ -569,6 +646,7 @@ qb_status do_step(qb_plan_s* pl, void* W, const double* B, double dt, int nsteps
     if (!hip_ok(hipGetLastError(), "heun launch")) return QB_EHIP;
     if (rec && !hip_ok(hipMemcpyAsync(rec + 8 * n, cur, sb, hipMemcpyDeviceToDevice, s), "trace copy"))
       return QB_EHIP;
+    if (inflow && !wall_inflow<T>(pl, cur, 0.5 * dt, inflow + (size_t)it * 7, true, s)) return QB_EHIP;
     if (!transport<T>(pl, cur, tmp, 0.5 * dt, s)) return QB_EHIP;
     if (mom && !moments<T>(pl, cur, mom + (it + 1) * mstride, s)) return QB_EHIP;
   }
@@ -1010,6 +1088,16 @@ qb_status qb_step(qb_plan plan, void* W, const double* B, double dt, int32_t nst
   hipStream_t s = (hipStream_t)stream;
   if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, moments_out, nullptr, s);
   return do_step<float>(plan, W, B, dt, nsteps, moments_out, nullptr, s);
+}
+
+qb_status qb_step_fluxes(qb_plan plan, void* W, const double* B, double dt, int32_t nsteps, double* moments_out,
+                         double* inflow, void* stream) {
+  if (!plan || !W || !inflow || nsteps < 0) return QB_EINVAL;
+  qb_status st = check_cfl(plan, 0.5 * dt);
+  if (st != QB_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (plan->prob.precision == QB_F64) return do_step<double>(plan, W, B, dt, nsteps, moments_out, nullptr, s, inflow);
+  return do_step<float>(plan, W, B, dt, nsteps, moments_out, nullptr, s, inflow);
 }
 
 qb_status qb_plan_enable_adjoint(qb_plan plan) {

@@ -82,3 +82,4 @@ def test_null_arguments_rejected():
     assert lib.qb_plan_set_scheme(None, 0, 0) == _lib.QB_EINVAL
     assert lib.qb_probe_fma(0, 1, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_probe_copy(None, None, 16, 1, None, None) == _lib.QB_EINVAL
+    assert lib.qb_step_fluxes(None, None, None, 1e-3, 1, None, None, None) == _lib.QB_EINVAL
