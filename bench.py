@@ -102,6 +102,33 @@ def measure_ceilings():
     return c
 
 
+def equilibrium_residual(wl):
+    """max |C[W_FD]| over the velocity grid for the Fermi-Dirac state
+    (beta = 1, mu = 0; C vanishes on it up to discretisation, Sec. 2) on the
+    slab's grid and quadrature, relative to max |C| of the slab's perturbed
+    initial cells, in float64 and float32 (the float32 figure shows the
+    rounding floor of the bulk path)."""
+    import torch
+    import paper_1408_1782_amd as qb
+    import workloads
+
+    v = workloads.velocity_axis(wl.N, wl.L)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    f = workloads.fd_occupation(vx, vy, 1.0, 0.0)
+    fd = np.zeros((1, wl.N, wl.N, 2, 2), np.complex128)
+    fd[0, ..., 0, 0] = fd[0, ..., 1, 1] = f
+    out = {}
+    for precision in ("f64", "f32"):
+        cdt = torch.complex128 if precision == "f64" else torch.complex64
+        plan = qb.Plan(qb.Problem(4, wl.N, wl.J, wl.M, wl.L, wl.R, precision))
+        W = torch.from_numpy(np.concatenate([fd, wl.W0[:3]])).to(cdt).cuda().contiguous()
+        C = plan.collision(W).cpu().numpy()
+        plan.close()
+        out[precision] = float(np.abs(C[0]).max() / np.abs(C[1:]).max())
+    log(f"equilibrium residual: {out}")
+    return out
+
+
 def run_gpu(wl, precision, steps, warmup):
     import torch
     import paper_1408_1782_amd as qb
@@ -466,6 +493,7 @@ def main():
             "moments": {name: nrm(fin32["moments"][:, k], fin64["moments"][:, k])
                         for k, name in enumerate(("rho0", "rho1", "rho2", "rho3", "p_x", "p_y", "energy"))},
         }
+    out["equilibrium_residual"] = equilibrium_residual(wl)
     out["adjoint_forward_ratio"] = None
     if args.adj_steps > 0:
         adj = run_adjoint(args.adj_steps, args.adj_every)
