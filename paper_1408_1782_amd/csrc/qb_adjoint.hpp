@@ -162,8 +162,11 @@ __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz) {
 //   forward  a_j = inv2(in_j w_hat_g), c_j = fwd2(f0 a_j), field = Re inv2(sum_j out_j c_j)
 //   reverse  d = conj(F) field_bar;  b_j = F(out_j d);
 //            f0_bar += Re(a_j b_j);  w_hat_g_bar += in_j conj(F)(f0 b_j)
-// Task 7 (I_2):  S = sum_j sum_mu e_mu A_j,mu B_j,mu with A + iB = inv2(w_hat_mu (psi_j + i psi'_j)):
+// Tasks 7..10 (I_2, one Pauli component mu = task - 7 each, so that every
+// task does three transforms per j):
+//            S = sum_j sum_mu e_mu A_j,mu B_j,mu with A + iB = inv2(w_hat_mu (psi_j + i psi'_j)):
 //            w_hat_mu_bar += psi_j conj(F)(S_bar e_mu B) + psi'_j conj(F)(S_bar e_mu A)
+constexpr int kTermsVjpTasks = 11;
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d) {
   using K = Kern<T, P, E>;
@@ -171,13 +174,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
-  const int cell = blockIdx.x / 8;
-  const int task = blockIdx.x % 8;
+  const int cell = blockIdx.x / kTermsVjpTasks;
+  const int task = blockIdx.x % kTermsVjpTasks;
   const unsigned vo = threadIdx.x * S;
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
   const rsrc_t ra = mkbuf(d.acot + (size_t)cell * 16 * K::FSZ, 16 * K::FSZ);
-  const rsrc_t rt = mkbuf(d.tsb + ((size_t)cell * 8 + task) * 2 * K::FSZ, 2 * K::FSZ);
+  const rsrc_t rt = mkbuf(d.tsb + ((size_t)cell * kTermsVjpTasks + task) * 2 * K::FSZ, 2 * K::FSZ);
   const size_t tabn = (size_t)d.J * K::FSZ;
   if (task < 7) {
     const int g = task < 3 ? task + 1 : task - 3;
@@ -260,11 +263,11 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
     const T wj = (T)(kPi / d.J);
     const rsrc_t rps = mkbuf(d.psi, tabn);
     const rsrc_t rpp = mkbuf(d.psip, tabn);
+    const int mu = task - 7;
 #pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
       const unsigned tj = j * K::FSZ;
-#pragma unroll 1
-      for (int mu = 0; mu < 4; ++mu) {
+      {
         const unsigned fm = 2 * mu * K::FSZ;
         const rsrc_t rg = mkbuf(d.gspec + ((size_t)cell * 11 + 7 + mu) * 2 * K::FSZ, 2 * K::FSZ);
         T zr[E], zi[E];

@@ -342,7 +342,7 @@ bool build_adjoint(qb_plan_s* pl) {
     if (!pl->alloc(q, st)) return false;
   return pl->alloc(&pl->lamP, C * 4 * FSZ * b) && pl->alloc(&pl->acot, C * 16 * FSZ * b) &&
          pl->alloc(&pl->gspec, C * 22 * FSZ * b) && pl->alloc(&pl->gf0, C * 7 * FSZ * b) &&
-         pl->alloc(&pl->tsb, C * 16 * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
+         pl->alloc(&pl->tsb, C * 2 * qb::kTermsVjpTasks * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
          pl->alloc(&pl->i3sb, C * J * 4 * FSZ * b) && pl->alloc(&pl->gsum, C * 8 * FSZ * b) &&
          pl->alloc(&pl->i3t, C * J * 4 * FSZ * b) && pl->alloc(&pl->lamh, C * 4 * FSZ * b) &&
          pl->alloc(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&

@@ -45,7 +45,7 @@ bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int
   hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, cell0);
   const size_t nel = (size_t)ncells * P * P;
   hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
-  hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * qb::kTermsVjpTasks), dim3(NT), 0, s, d);
   pl->end(id, s);
   id = pl->begin(QB_K_I3_ADJOINT, s);
   if (pl->vjp_variant == 2)
