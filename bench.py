@@ -390,6 +390,126 @@ def run_convergence(precision="f64"):
     }
 
 
+PHYSICS_RUNS = ("E2", "E3", "E4", "E5", "E6i", "E6ii")
+
+
+def _rho_matrix(m):
+    """2x2 spin density sum_mu rho_mu sigma_mu from moment columns 0..3."""
+    import workloads
+    return np.einsum("...m,mij->...ij", m[..., :4], workloads.SIGMA)
+
+
+def _spin_basis(rho):
+    """Eigenbasis of a 2x2 spin density as U = [e_up, e_down] (columns)."""
+    lam, V = np.linalg.eigh(rho)
+    return V[:, ::-1]
+
+
+def run_physics(name, precision="f64", samples=20, t_end=None, Nx=None, N=32):
+    """One of the simulations of Sec. 5.2 and 5.3 on the GPU (workloads
+    physics_run), sampled `samples` times: total moments, entropy and its
+    production, relative entropies (to the global equilibrium where the
+    moments fix one, and to the local fits), eigenvalue range; for the
+    homogeneous run the L1 distance to the equilibrium, for the wall runs
+    the change of the state between samples and the final x-profiles of the
+    density, local temperature and local entropy."""
+    import torch
+    import paper_1408_1782_amd as qb
+    import workloads
+
+    wl = workloads.physics_run(name, N=N, Nx=Nx, t_end=t_end)
+    cd = torch.complex128 if precision == "f64" else torch.complex64
+    prob = qb.Problem(wl.Nx, wl.N, wl.J, wl.M, wl.L, wl.R, precision,
+                      qb.BC.from_workload(wl.left), qb.BC.from_workload(wl.right))
+    plan = qb.Plan(prob)
+    W = torch.from_numpy(wl.W0).to(cd).cuda().contiguous()
+    B = torch.from_numpy(wl.B).cuda().contiguous()
+    dx, h2 = 1.0 / wl.Nx, (2 * wl.L / wl.N) ** 2
+    periodic = wl.left.kind == "periodic"
+    m0 = plan.moments(W).cpu().numpy()
+    tot0 = dx * m0.sum(0)
+
+    # equilibrium fixed by the conserved totals: the local fit of the
+    # cell-averaged state (moments are linear in W), spin basis of its density
+    fd, fd_fit = None, None
+    if periodic:
+        one = qb.Plan(qb.Problem(1, wl.N, wl.J, wl.M, wl.L, wl.R, precision))
+        avg = W.mean(dim=0, keepdim=True).contiguous()
+        d = one.diagnostics(avg).cpu().numpy()[0]
+        one.close()
+        fd_fit = {"kT": d[6], "mu_up": d[7], "mu_down": d[8], "u": [d[9], d[10]]}
+        U = _spin_basis(_rho_matrix(tot0))
+        fd_fit["U"] = [[[z.real, z.imag] for z in row] for row in U]
+        if wl.Nx > 1:
+            fd = (1.0 / d[6], d[7], d[8], U)
+        if wl.Nx == 1:
+            v = workloads.velocity_axis(wl.N, wl.L)
+            vx, vy = np.meshgrid(v - d[9], v - d[10], indexing="ij")
+            D = np.zeros((wl.N, wl.N, 2, 2), np.complex128)
+            D[..., 0, 0] = workloads.fd_occupation(vx, vy, 1.0 / d[6], d[7])
+            D[..., 1, 1] = workloads.fd_occupation(vx, vy, 1.0 / d[6], d[8])
+            wfd = _pauli_np(U @ D @ np.conj(U.T))
+
+    every = max(1, wl.steps // samples)
+    series = {k: [] for k in ("t", "density_rel_dev", "trace_density_rel_dev", "momentum_dev", "energy_rel_dev", "entropy",
+                              "entropy_production", "rel_entropy_global", "rel_entropy_local",
+                              "eig_min", "eig_max", "l1_to_fd", "state_change_rate")}
+    prev = None
+    done = 0
+    t0 = time.perf_counter()
+    gpu_s = 0.0
+    while True:
+        C = plan.collision(W)
+        dg = plan.diagnostics(W, C, fd=fd).cpu().numpy()
+        m = plan.moments(W).cpu().numpy()
+        tot = dx * m.sum(0)
+        Wh = W.cpu().numpy()
+        series["t"].append(done * wl.dt)
+        series["density_rel_dev"].append(float(np.linalg.norm(_rho_matrix(tot) - _rho_matrix(tot0))
+                                               / np.linalg.norm(_rho_matrix(tot0))))
+        series["trace_density_rel_dev"].append(float(abs(tot[0] - tot0[0]) / abs(tot0[0])))
+        series["momentum_dev"].append(float(np.abs(tot[4:6] - tot0[4:6]).max() / (2 * tot0[0])))
+        series["energy_rel_dev"].append(float(abs(tot[6] - tot0[6]) / abs(tot0[6])))
+        series["entropy"].append(float(dx * dg[:, 0].sum()))
+        series["entropy_production"].append(float(dx * dg[:, 1].sum()))
+        series["rel_entropy_global"].append(float(dx * dg[:, 2].sum()) if fd is not None else None)
+        series["rel_entropy_local"].append(float(dx * dg[:, 3].sum()))
+        series["eig_min"].append(float(dg[:, 4].min()))
+        series["eig_max"].append(float(dg[:, 5].max()))
+        if periodic and wl.Nx == 1:
+            series["l1_to_fd"].append(float(h2 * np.abs(_pauli_np(Wh[0]) - wfd).sum()))
+        else:
+            series["l1_to_fd"].append(None)
+        if prev is not None:
+            series["state_change_rate"].append(float(np.abs(Wh - prev).max() / (every * wl.dt)))
+        else:
+            series["state_change_rate"].append(None)
+        prev = Wh
+        if done >= wl.steps:
+            break
+        k = min(every, wl.steps - done)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        plan.step(W, B, wl.dt, k)
+        torch.cuda.synchronize()
+        gpu_s += time.perf_counter() - a
+        done += k
+        log(f"[physics {name}] t = {done * wl.dt:.3f}  S = {series['entropy'][-1]:.10f}")
+    x = workloads.cell_centres(wl.Nx)
+    out = {
+        "run": name, "precision": precision, "Nx": wl.Nx, "N": wl.N, "J": wl.J, "M": wl.M, "L": wl.L,
+        "R": wl.R, "dt": wl.dt, "steps": wl.steps, "t_end": wl.steps * wl.dt,
+        "walls": [wl.left.kind, wl.right.kind],
+        "step_seconds": gpu_s, "cells_steps_per_s": wl.Nx * wl.steps / gpu_s if gpu_s > 0 else None,
+        "equilibrium_fit": fd_fit, "series": series,
+        "final": {"x": x.tolist(), "rho": m[:, :4].T.tolist(), "kT": dg[:, 6].tolist(),
+                  "entropy": dg[:, 0].tolist(), "u_x": dg[:, 9].tolist()},
+        "wall_seconds": time.perf_counter() - t0,
+    }
+    plan.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -408,6 +528,10 @@ def main():
                     help="run a 512 MiB device copy first (scale for HBM byte counters)")
     ap.add_argument("--convergence", action="store_true",
                     help="print the J / M / N convergence study of C_c and C_d instead of the bench line")
+    ap.add_argument("--physics", choices=PHYSICS_RUNS, default=None,
+                    help="run one of the paper's simulations (Sec. 5.2, 5.3) and print its record")
+    ap.add_argument("--t-end", type=float, default=None, help="end time of the --physics run")
+    ap.add_argument("--vgrid", type=int, default=32, help="velocity grid N of the --physics run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -415,6 +539,9 @@ def main():
         sys.exit(2)
     if args.convergence:
         print(json.dumps(run_convergence()), flush=True)
+        return
+    if args.physics:
+        print(json.dumps(run_physics(args.physics, t_end=args.t_end, N=args.vgrid)), flush=True)
         return
 
     import workloads

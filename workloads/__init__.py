@@ -199,3 +199,103 @@ def validation_state(N, L=L_BOX):
     W[..., 0, 1] = w1 - 1j * w2
     W[..., 1, 0] = w1 + 1j * w2
     return W
+
+
+# ------------------------------------------------------------------ physics runs (Sec. 5.2, 5.3)
+def rotation_generator(vx, vy):
+    """X(v) of eq. W0homogeneous as [..., 2, 2]: sin(v_y^2) 1 + (v_x - 1) s1
+    + 2 / (v_x^2 + |v_y| + 1) s2 + cos(v_x + v_y / 2) s3."""
+    c = (np.sin(vy**2), vx - 1.0, 2.0 / (vx**2 + np.abs(vy) + 1.0), np.cos(vx + 0.5 * vy))
+    return sum(ci[..., None, None] * SIGMA[i] for i, ci in enumerate(c))
+
+
+def _expm_herm(X, s):
+    """exp(s X) for Hermitian 2x2 X and complex scalar s (eigendecomposition)."""
+    lam, V = np.linalg.eigh(X)
+    return (V * np.exp(s * lam)[..., None, :]) @ np.conj(np.swapaxes(V, -1, -2))
+
+
+HOMOGENEOUS_U0 = np.array([[np.cos(np.pi / 5), -1j * np.sin(np.pi / 5)],
+                           [np.sin(np.pi / 5), 1j * np.cos(np.pi / 5)]])
+
+
+def rotated_fd_state(N, kT, mu_up, mu_down, v0, L=L_BOX):
+    """exp(-i X(v)) U0 diag(f_up, f_down)(v - v0) U0^* exp(i X(v)), the
+    Fermi-Dirac state rotated by v-dependent unitaries (eq. W0homogeneous);
+    kT, mu_up, mu_down and v0 = (v0x, v0y) may be arrays over cells (a
+    leading axis), giving [Nx, N, N, 2, 2], else [N, N, 2, 2]."""
+    v = velocity_axis(N, L)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    kT, mu_up, mu_down = (np.asarray(a, dtype=float)[..., None, None] for a in (kT, mu_up, mu_down))
+    v0x = np.asarray(v0[0], dtype=float)[..., None, None]
+    v0y = np.asarray(v0[1], dtype=float)[..., None, None]
+    e = 0.5 * ((vx - v0x) ** 2 + (vy - v0y) ** 2)
+    D = np.zeros(np.broadcast(e, mu_up).shape + (2, 2), np.complex128)
+    D[..., 0, 0] = 1.0 / (np.exp((e - mu_up) / kT) + 1.0)
+    D[..., 1, 1] = 1.0 / (np.exp((e - mu_down) / kT) + 1.0)
+    Q = _expm_herm(rotation_generator(vx, vy), -1j) @ HOMOGENEOUS_U0
+    return Q @ D @ np.conj(np.swapaxes(Q, -1, -2))
+
+
+def fd_wall_state(N, inv_kT, mu_up, mu_down, U, L=L_BOX):
+    """U diag(f_up, f_down) U^* at rest on the velocity grid (eq. W_FermiDirac)."""
+    v = velocity_axis(N, L)
+    vx, vy = np.meshgrid(v, v, indexing="ij")
+    D = np.zeros((N, N, 2, 2), np.complex128)
+    D[..., 0, 0] = fd_occupation(vx, vy, inv_kT, mu_up)
+    D[..., 1, 1] = fd_occupation(vx, vy, inv_kT, mu_down)
+    U = np.asarray(U, np.complex128)
+    return U @ D @ np.conj(U.T)
+
+
+ROT45 = np.array([[1.0, -1.0], [1.0, 1.0]], np.complex128) / np.sqrt(2.0)
+
+
+def physics_run(name, N=32, Nx=None, t_end=None):
+    """The simulations of Sec. 5.2 and 5.3 (N = 32, L = 12, J = M = 32,
+    R = 7.5), as workloads; t_end sets the number of steps.
+      E2   homogeneous relaxation (one periodic cell), eq. W0homogeneous with
+           kT = 5/4, mu = (1, 3/2), v0 = (0.4, -0.1); dt = 0.001.
+      E3   periodic, dx = 0.1, dt = 0.008; the same state with x-dependent
+           kT = 5/4 + cos(2 pi x) / 4, mu_up = 1 + cos(2 pi x) / 2,
+           mu_down = 3/2 - cos(2 pi x) / 2, v0 = (0.4, -0.1) sin(2 pi x).
+      E4   E3 with B(x) = (0, cos 2 pi x, sin 2 pi x) (eq. Bext_rot), t = 1.
+      E5   Dirichlet walls of Table 1, dx = 0.025, dt = 0.002.
+      E6i, E6ii  Maxwell walls of Table 2 (alpha = 0.4), dx = 0.025,
+           dt = 0.002, t = 4.
+    The wall runs start from the Fermi-Dirac state at rest whose inverse
+    temperature and chemical potentials are the means of the two walls'
+    (spin basis 1)."""
+    periodic = BC("periodic")
+    if name == "E2":
+        Nx = Nx or 1
+        W = np.broadcast_to(rotated_fd_state(N, 1.25, 1.0, 1.5, (0.4, -0.1)), (Nx, N, N, 2, 2)).copy()
+        dt = 1e-3
+        return Workload(name, Nx, N, L_BOX, R_TRUNC, J_ANGLES, N, dt, int(round((t_end or 1.0) / dt)),
+                        W, np.zeros((Nx, 3)), periodic, periodic)
+    if name in ("E3", "E4"):
+        Nx = Nx or 10
+        x = cell_centres(Nx)
+        c, s = np.cos(2 * np.pi * x), np.sin(2 * np.pi * x)
+        W = rotated_fd_state(N, 1.25 + 0.25 * c, 1.0 + 0.5 * c, 1.5 - 0.5 * c, (0.4 * s, -0.1 * s))
+        B = np.zeros((Nx, 3))
+        if name == "E4":
+            B = np.stack([np.zeros(Nx), c, s], axis=1)
+        dt = 0.008
+        return Workload(name, Nx, N, L_BOX, R_TRUNC, J_ANGLES, N, dt,
+                        int(round((t_end or (1.0 if name == "E4" else 2.0)) / dt)), W, B, periodic, periodic)
+    walls = {
+        "E5": (BC("dirichlet", 0.8, 1.5, -1.5), BC("dirichlet", 1.2, 1.5, -1.5, ROT45)),
+        "E6i": (BC("maxwell", 0.6, -0.4, 1.8, alpha=0.4), BC("maxwell", 1.1, 1.3, -0.9, alpha=0.4)),
+        "E6ii": (BC("maxwell", 1.0, 1.5, -1.5, alpha=0.4), BC("maxwell", 1.0, 1.5, -1.5, ROT45, alpha=0.4)),
+    }
+    if name in walls:
+        Nx = Nx or 40
+        left, right = walls[name]
+        mid = fd_wall_state(N, 0.5 * (left.inv_kT + right.inv_kT), 0.5 * (left.mu_up + right.mu_up),
+                            0.5 * (left.mu_down + right.mu_down), np.eye(2))
+        W = np.broadcast_to(mid, (Nx, N, N, 2, 2)).copy()
+        dt = 0.002
+        return Workload(name, Nx, N, L_BOX, R_TRUNC, J_ANGLES, N, dt, int(round((t_end or 4.0) / dt)),
+                        W, np.zeros((Nx, 3)), left, right)
+    raise ValueError(name)
