@@ -563,7 +563,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         }
         eng.inv2(zr, zi);
         const T e0 = m0 == 0 ? wgt : -wgt;
-        const T ew = nu == 0 ? wgt : -wgt;  // c eta_nu
+        // c eta_nu, zero for the middle node of an odd M (no partner): the
+        // partner sums then take zeros instead of a branch per element
+        const T ew = !paired ? (T)0 : (nu == 0 ? wgt : -wgt);
         const unsigned pt = PF ? lds_fetch_wait() : 0u;
         const bool res = KRES > 0 && nu < KRES;
         T* const al = acc + (KRES > 0 && res ? nu * K::FSZ : 0) + tid;
@@ -583,19 +585,22 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           }
           const unsigned off = (nu * K::FSZ + o) * S;
           T v = e0 * sa * zr[n] - wgt * sb * zi[n];
+          // the accumulator is read on the first pass too (in bounds, not
+          // yet written) and the value dropped by a select: uniform branches
+          // here would cut the element loop into separately scheduled blocks
           if (KRES > 0 && res) {
-            if (!first) v += al[KRES > 0 ? o : 0];
+            const T prev = al[KRES > 0 ? o : 0];
+            v += first ? (T)0 : prev;
             al[KRES > 0 ? o : 0] = v;
           } else {
-            if (!first) v += PF ? pf[PF ? o + pt : 0] : bld<T>(ro, vo, off);
+            const T prev = PF ? pf[PF ? o + pt : 0] : bld<T>(ro, vo, off);
+            v += first ? (T)0 : prev;
             bst<T>(ro, v, vo, off);
           }
           if constexpr (PAIR) {
-            if (paired) {
-              const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
-              pa[PAIR ? n : 0] += sa_sign * wv * zr[n];
-              pb[PAIR ? n : 0] += wv * zi[n];
-            }
+            const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
+            pa[PAIR ? n : 0] += sa_sign * wv * zr[n];
+            pb[PAIR ? n : 0] += wv * zi[n];
           }
           if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);
         }
@@ -619,10 +624,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
           T xr, xi;
           cmul(zr[k], zi[k], er, -ei, xr, xi);
-          if (m != 0) {
-            xr += PF ? pf[PF ? o + pt : 0] : bld<T>(rp, vo, (fr + o) * S);
-            xi += bld<T>(rp, vo, (fi + o) * S);
-          }
+          const T pr0 = PF ? pf[PF ? o + pt : 0] : bld<T>(rp, vo, (fr + o) * S);
+          const T pi0 = bld<T>(rp, vo, (fi + o) * S);
+          xr += m != 0 ? pr0 : (T)0;
+          xi += m != 0 ? pi0 : (T)0;
           bst<T>(rp, xr, vo, (fr + o) * S);
           bst<T>(rp, xi, vo, (fi + o) * S);
         }
