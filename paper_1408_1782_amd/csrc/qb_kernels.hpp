@@ -328,10 +328,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
         const unsigned o = k * K::NT;
         const T a = bld<T>(rout, vo, (tj + o) * S);
         T ar = a * zr[k], ai = a * zi[k];
-        if (j != 0) {
-          ar += bld<T>(ra, vo, o * S);
-          ai += bld<T>(ra, vo, (K::FSZ + o) * S);
-        }
+        // read at j = 0 too (not yet written) and dropped by a select
+        const T pr = bld<T>(ra, vo, o * S), pi = bld<T>(ra, vo, (K::FSZ + o) * S);
+        ar += j != 0 ? pr : (T)0;
+        ai += j != 0 ? pi : (T)0;
         bst<T>(ra, ar, vo, o * S);
         bst<T>(ra, ai, vo, (K::FSZ + o) * S);
       }
