@@ -92,3 +92,16 @@ def test_wall_runs_keep_the_temperature_between_the_walls(name, lo, hi):
     kT = np.array(r["final"]["kT"])
     assert np.all(np.isfinite(kT))
     assert kT.min() >= lo and kT.max() <= hi
+
+
+def test_resolution_shrinks_the_drift_and_the_eigenvalue_dip():
+    """The homogeneous run at the paper's N = 32 under-resolves the rotated
+    state; at N = 64 the energy drift falls by orders of magnitude (to the
+    level the paper plots) and the dip of the smallest eigenvalue below
+    zero shrinks."""
+    r32 = bench.run_physics("E2", t_end=0.02, samples=2, N=32)["series"]
+    r64 = bench.run_physics("E2", t_end=0.02, samples=2, N=64)["series"]
+    assert r64["energy_rel_dev"][-1] < 1e-2 * r32["energy_rel_dev"][-1]
+    assert r64["energy_rel_dev"][-1] < 1e-5
+    assert r64["momentum_dev"][-1] < 1e-2 * r32["momentum_dev"][-1]
+    assert r32["eig_min"][-1] < 0 and r64["eig_min"][-1] > 0.25 * r32["eig_min"][-1]
