@@ -463,6 +463,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   // own elements, so no barrier guards them
   constexpr int KRES = I3Regs<T, P, E>::template lds_acc<PAIR, K::LDS>();
   __shared__ T acc[KRES > 0 ? KRES * K::FSZ : 1];
+  // elements between scheduling barriers in the element loops, which bound
+  // the loads in flight (measured: 4 at P = 128, 8 at P = 64)
+  constexpr int SG = P >= 128 ? 4 : 8;
   const unsigned tid = threadIdx.x;
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
@@ -551,7 +554,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
             sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
           zr[n] = bld<T>(rw, vo, (m0 * K::FSZ + o) * S) * sv;
           zi[n] = bld<T>(rw, vo, (m1 * K::FSZ + o) * S) * sv;
-          if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);   // bound the loads in flight
+          if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
         eng.fwd2(zr, zi);
 #pragma unroll
@@ -559,7 +562,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           const T a = bld<T>(rm, vo, (k * K::NT) * S);
           zr[k] *= a;
           zi[k] *= a;
-          if ((k & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+          if (k % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
         eng.inv2(zr, zi);
         const T e0 = m0 == 0 ? wgt : -wgt;
@@ -602,7 +605,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
             pa[PAIR ? n : 0] += sa_sign * wv * zr[n];
             pb[PAIR ? n : 0] += wv * zi[n];
           }
-          if ((n & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+          if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }
       // spectrum of the partner sums: conj(phase) fwd2(pa + i pb), accumulated
