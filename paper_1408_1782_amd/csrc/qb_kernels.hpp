@@ -504,6 +504,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
         zr[k] = ar - bi;
         zi[k] = ai + br;
+        if (k % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
       }
       eng.inv2(zr, zi);
 #pragma unroll
@@ -633,6 +634,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           xi += m != 0 ? pi0 : (T)0;
           bst<T>(rp, xr, vo, (fr + o) * S);
           bst<T>(rp, xi, vo, (fi + o) * S);
+          if (k % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       } else if (m == 0) {
         // no partner spectrum (unpaired kernel, or a single node)
