@@ -406,3 +406,116 @@ def test_step_reductions():
     s = ostep.step(w, np.zeros((6, 3)), 2e-3, L, 0.0, J, M, per, per, zero_t)
     ref = tp.transport_step(tp.transport_step(w, 1e-3, per, per, L), 1e-3, per, per, L)
     assert np.allclose(s, ref, atol=1e-15)
+
+
+# ---------------------------------------------------------------- wall ghost cells
+# Sec. 2 boundary conditions inside eq. slopeLimiterStep (Sec. 4), read as
+# two ghost cells per wall that hold the inflow state at entering v_x and a
+# copy of the adjacent cell otherwise.  The expected values below are closed
+# forms of one step, written from the grid alone (explicit loops over rows,
+# no call of the oracle's ghost or inflow helpers).
+
+def _rows(N):
+    """(i, v_x) for every row of the velocity grid v_x = (2L/N)(i - N/2)."""
+    h = 2 * L / N
+    return [(i, h * (i - N // 2)) for i in range(N)]
+
+
+def _const_field(N, c):
+    return np.broadcast_to(np.asarray(c, float), (N, N, 4)).copy()
+
+
+@pytest.mark.parametrize("side", ["left", "right"])
+def test_dirichlet_wall_into_empty_slab(side):
+    """Zero interior, Dirichlet state Phi on one wall (the other wall a
+    zero Dirichlet state): every one-sided difference next to the wall has
+    the inflow jump on one side and zero on the other, so every limited
+    slope vanishes and the step is first-order upwind.  The wall cell then
+    holds (dt/dx) |v_x| Phi on the rows entering through that wall and 0 on
+    every other row; every other cell stays 0."""
+    Nx, N = 7, 8
+    rng = np.random.default_rng(21)
+    phi = rng.uniform(0.05, 0.4, (N, N, 4))
+    zero = np.zeros((N, N, 4))
+    bc_phi = {"kind": "dirichlet", "state": phi}
+    bc_zero = {"kind": "dirichlet", "state": zero}
+    bl, br = (bc_phi, bc_zero) if side == "left" else (bc_zero, bc_phi)
+    dx = 1.0 / Nx
+    dt = 0.8 * dx / L                       # CFL number 0.8 on the fastest row
+    w1 = tp.transport_step(np.zeros((Nx, N, N, 4)), dt, bl, br, L)
+    wall = 0 if side == "left" else Nx - 1
+    expect = np.zeros((Nx, N, N, 4))
+    for i, vx in _rows(N):
+        entering = vx > 0 if side == "left" else vx < 0
+        if entering:
+            expect[wall, i] = (dt / dx) * abs(vx) * phi[i]
+    assert np.array_equal(np.delete(w1, wall, axis=0), np.delete(expect, wall, axis=0))
+    assert np.allclose(w1[wall], expect[wall], rtol=1e-14, atol=0)
+    assert np.any(expect[wall] != 0)
+
+
+def test_dirichlet_walls_uniform_interior():
+    """Interior state U equal in every cell and velocity, Dirichlet states
+    Phi_l, Phi_r: every limited slope vanishes (all interior differences are
+    zero and the wall differences meet a zero on their other side), so the
+    wall cells relax toward the wall states at the upwind rate,
+    U + (dt/dx) |v_x| (Phi - U), on the entering rows, and everything else
+    keeps U."""
+    Nx, N = 6, 8
+    rng = np.random.default_rng(22)
+    U = np.array([0.45, 0.05, -0.1, 0.02])
+    phl = rng.uniform(0.05, 0.4, (N, N, 4))
+    phr = rng.uniform(0.05, 0.4, (N, N, 4))
+    dx = 1.0 / Nx
+    dt = 0.6 * dx / L
+    w = np.broadcast_to(U, (Nx, N, N, 4)).copy()
+    w1 = tp.transport_step(w, dt, {"kind": "dirichlet", "state": phl},
+                           {"kind": "dirichlet", "state": phr}, L)
+    expect = w.copy()
+    for i, vx in _rows(N):
+        if vx > 0:
+            expect[0, i] = U + (dt / dx) * vx * (phl[i] - U)
+        if vx < 0:
+            expect[Nx - 1, i] = U + (dt / dx) * (-vx) * (phr[i] - U)
+    assert np.allclose(w1, expect, rtol=0, atol=1e-15)
+
+
+def test_maxwell_walls_closed_form():
+    """Maxwell walls (Sec. 2) on a slab whose every cell holds the same
+    state U(v_x), which varies with v_x only (so that the mirror row
+    matters), and a wall state G constant in v.  The inflow state at an
+    entering row i is (1 - alpha) U(row N - i) + alpha G Fbar / Z with the
+    outgoing number flux Fbar = h^2 sum_out 2 u_0 |v_x| and the incoming
+    flux of G, Z = h^2 sum_in 2 g_0 |v_x|, both sums written out below over
+    the rows (the row v_x = -L has no mirror: it enters at neither wall's
+    sums on the right and keeps U).  Every limited slope vanishes as in the
+    Dirichlet case, so the wall cells take U + (dt/dx) |v_x| (state - U) on
+    the entering rows."""
+    Nx, N = 5, 8
+    h = 2 * L / N
+    rng = np.random.default_rng(23)
+    Urow = np.column_stack([rng.uniform(0.3, 0.6, N), rng.uniform(-0.1, 0.1, (N, 3))])
+    U = np.broadcast_to(Urow[:, None, :], (N, N, 4))
+    G = np.array([0.35, 0.0, 0.04, -0.03])
+    dx = 1.0 / Nx
+    dt = 0.7 * dx / L
+    for al, ar in ((0.0, 1.0), (0.4, 0.5), (1.0, 0.0)):
+        w = np.broadcast_to(U, (Nx, N, N, 4)).copy()
+        bl = {"kind": "maxwell", "state": _const_field(N, G), "alpha": al}
+        br = {"kind": "maxwell", "state": _const_field(N, G), "alpha": ar}
+        w1 = tp.transport_step(w, dt, bl, br, L)
+        expect = w.copy()
+        for side, alpha, cell in (("left", al, 0), ("right", ar, Nx - 1)):
+            if side == "left":
+                enter = [i for i, vx in _rows(N) if vx > 0]
+                leave = [i for i, vx in _rows(N) if vx < 0]
+            else:
+                enter = [i for i, vx in _rows(N) if vx < 0 and i > 0]
+                leave = [i for i, vx in _rows(N) if vx > 0]
+            vabs = {i: abs(vx) for i, vx in _rows(N)}
+            Fbar = h * h * sum(N * 2 * Urow[i, 0] * vabs[i] for i in leave)
+            Z = h * h * sum(N * 2 * G[0] * vabs[i] for i in enter)
+            for i in enter:
+                state = (1 - alpha) * Urow[N - i] + alpha * G * Fbar / Z
+                expect[cell, i] = Urow[i] + (dt / dx) * vabs[i] * (state - Urow[i])
+        assert np.allclose(w1, expect, rtol=0, atol=1e-14), (al, ar)
