@@ -12,7 +12,10 @@
  * ---------------------------------------
  * Memory.  Every array argument is a DEVICE pointer (e.g. from torch) unless
  *   noted; calls are asynchronous on `stream` (a hipStream_t; NULL = default
- *   stream).  The library never frees caller memory.
+ *   stream).  The library never allocates or frees device memory: plans and
+ *   batches are laid out in a workspace the caller allocates (size from
+ *   qb_workspace_bytes / qb_batch_workspace_bytes / qb_adjoint_workspace_bytes)
+ *   and keeps alive, unmodified, until the plan or batch is destroyed.
  * State layout.  W and C are [cells][N][N][2][2] complex, row-major, complex
  *   interleaved (re, im): complex128 for QB_F64 plans, complex64 for QB_F32.
  *   Only the Hermitian part of W is read (components w_mu =
@@ -24,7 +27,7 @@
  *   (eq. internal_energy plus the kinetic part), h = 2L/N.
  * Errors.  Every call validates its arguments before enqueuing anything;
  *   on error it returns a negative qb_status and enqueues nothing.
- *   QB_EHIP reports a failed HIP call (launch or allocation); the text of
+ *   QB_EHIP reports a failed HIP call (a launch or a copy); the text of
  *   the last error is available from qb_last_error().
  * Threads.  A plan may be used by one stream at a time; distinct plans are
  *   independent.
@@ -44,7 +47,7 @@ typedef enum {
   QB_EINVAL = -1,     /* bad argument (null pointer, size, range)          */
   QB_ENOTSUP = -2,    /* valid but unsupported (N not 16/32/64, odd J)      */
   QB_ECFL = -3,       /* (dt/2) max|v_x| / dx > 1 for the transport step    */
-  QB_EWORKSPACE = -4, /* more cells than the plan was created for           */
+  QB_EWORKSPACE = -4, /* workspace too small, or more cells than the plan holds */
   QB_EHIP = -5        /* HIP runtime error                                  */
 } qb_status;
 
@@ -96,18 +99,33 @@ typedef struct {
 
 typedef struct qb_plan_s* qb_plan;
 
-/* Create a plan: validates the problem, builds the quadrature tables of
- * Sec. 3.2 (theta grids, phi_R, psi_R, omega_G, omega_H, Gauss-Legendre
- * nodes, modulation phases) on the host in float64, and allocates every
- * device buffer the other calls need for up to Nx cells on the current
- * HIP device.  Synchronous.  *out receives the plan (NULL on error). */
-qb_status qb_plan_create(const qb_problem* problem, qb_plan* out);
+/* Device bytes of a plan's workspace for `problem` (0 if the problem is
+ * invalid): the quadrature tables of Sec. 3.2 for every compiled tile shape,
+ * the wall tables, the collision buffers for `max_cells` cells per
+ * collision launch (0: min(Nx, 512); larger Nx runs in chunks) and four
+ * state-sized buffers.  Pure host arithmetic; no HIP call. */
+size_t qb_workspace_bytes(const qb_problem* problem, int32_t max_cells);
 
-/* Free a plan and its device memory (synchronizes the device first). */
+/* Create a plan in the caller's device workspace (at least
+ * qb_workspace_bytes(problem, max_cells) bytes, any alignment the HIP
+ * allocator returns): validates the problem, builds the quadrature tables of
+ * Sec. 3.2 (theta grids, phi_R, psi_R, omega_G, omega_H, Gauss-Legendre
+ * nodes, modulation phases) on the host in float64 and copies them in.
+ * Allocates no device memory.  Synchronous.  The workspace belongs to the
+ * plan until qb_plan_destroy.  *out receives the plan (NULL on error).
+ * QB_EWORKSPACE if ws_bytes is too small, QB_EINVAL for a null workspace
+ * or a negative max_cells. */
+qb_status qb_plan_create(const qb_problem* problem, int32_t max_cells, void* workspace, size_t ws_bytes,
+                         qb_plan* out);
+
+/* Free the plan's host state (synchronizes the device first); the caller
+ * may then release the workspace. */
 qb_status qb_plan_destroy(qb_plan plan);
 
-/* Device bytes held by a plan. */
+/* Workspace bytes in use by a plan (its adjoint workspace included once
+ * enabled), and the number of cells one collision launch covers. */
 size_t qb_plan_bytes(qb_plan plan);
+int32_t qb_plan_chunk_cells(qb_plan plan);
 
 /* C = C[W] = C_c[W] + C_d[W] for `ncells` independent cells (Sec. 3.2):
  * the conservative part through the principal-value kernel G (eq. approxG)
@@ -279,10 +297,18 @@ qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, 
  * ------------------------------------------------------------------------- */
 typedef struct qb_batch_s* qb_batch;
 
-/* Create a batch of nprob problems (each valid for qb_plan_create; all with
- * the same precision, J, L and R; problems with equal N must have equal M).
- * Allocates all device memory (synchronous). */
-qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, qb_batch* out);
+/* Device bytes of the workspace of a batch of nprob problems (each valid for
+ * qb_plan_create; all with the same precision, J, L and R; problems with
+ * equal N must have equal M); 0 for an invalid batch. */
+size_t qb_batch_workspace_bytes(const qb_problem* problems, int32_t nprob);
+
+/* Create a batch in the caller's device workspace (at least
+ * qb_batch_workspace_bytes bytes; kept alive until qb_batch_destroy).
+ * Allocates no device memory; creates one non-blocking HIP stream on which
+ * QB_BATCH_GRAPH records its graphs.  Synchronous.  QB_EWORKSPACE if the
+ * workspace is too small. */
+qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, void* workspace, size_t ws_bytes,
+                          qb_batch* out);
 qb_status qb_batch_destroy(qb_batch batch);
 size_t qb_batch_bytes(qb_batch batch);
 
@@ -300,8 +326,8 @@ qb_status qb_batch_tune(qb_batch batch, void* stream);
  *   flags   : QB_BATCH_GRAPH records the launch sequence of the call in a HIP
  *             graph on first use and replays it while W, B, moments, dt and
  *             nsteps are unchanged (no HIP graph memset nodes are used).
- * QB_ECFL if (dt/2) L Nx_m > 1 for any problem.  The first call that asks
- * for moments with more snapshots than before allocates scratch for them. */
+ * QB_ECFL if (dt/2) L Nx_m > 1 for any problem.  Moments are written
+ * straight into each problem's array (no scratch). */
 qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, double dt, int32_t nsteps,
                         double* const* moments, int32_t flags, void* stream);
 
@@ -315,9 +341,16 @@ qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, 
  * forward state.
  * ------------------------------------------------------------------------- */
 
-/* Allocate the plan's adjoint workspace (synchronous, idempotent).  Every
- * call below returns QB_EWORKSPACE until this has succeeded. */
-qb_status qb_plan_enable_adjoint(qb_plan plan);
+/* Device bytes of the reverse-mode workspace of a plan (cotangent buffers
+ * of the collision pipeline and of the states). */
+size_t qb_adjoint_workspace_bytes(qb_plan plan);
+
+/* Lay out the reverse-mode buffers in a caller workspace of at least
+ * qb_adjoint_workspace_bytes(plan) bytes (kept alive until the plan is
+ * destroyed); allocates nothing.  Idempotent: once enabled, later calls
+ * return QB_OK and keep the first workspace.  Every call below returns
+ * QB_EWORKSPACE until this has succeeded. */
+qb_status qb_plan_enable_adjoint(qb_plan plan, void* workspace, size_t ws_bytes);
 
 /* G = C'(W)^T lam for `ncells` cells: the transpose of the linearization of
  * qb_collision at W applied to the cotangent lam of C (Sec. 3.2; C is a

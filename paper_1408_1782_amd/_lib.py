@@ -1,9 +1,12 @@
 """ctypes binding of libqb.so (include/qb.h): argument marshalling only.
 
 Every numerical step runs in the HIP library.  Tensors passed in must be
-contiguous CUDA (HIP) tensors of the dtype the plan expects; the binding
-checks shapes and dtypes, passes raw device pointers and the current torch
-stream, and raises QBError on any non-zero status.
+contiguous CUDA (HIP) tensors of the dtype the plan expects; every device
+buffer goes through one check (``_dev``: device, contiguity, dtype, shape)
+before any library call, the binding passes raw device pointers and the
+current torch stream, and raises QBError on any non-zero status.  The
+library allocates no device memory: the workspaces of plans and batches are
+torch tensors this module allocates and keeps alive beside the handles.
 """
 import ctypes
 import os
@@ -23,7 +26,11 @@ DIAG_NAMES = ("entropy", "entropy_production", "rel_entropy_global", "rel_entrop
 
 # names the header declares (checked by the CPU tests)
 EXPORTS = (
+    "qb_workspace_bytes",
     "qb_plan_create",
+    "qb_plan_chunk_cells",
+    "qb_adjoint_workspace_bytes",
+    "qb_batch_workspace_bytes",
     "qb_plan_destroy",
     "qb_plan_bytes",
     "qb_collision",
@@ -106,8 +113,17 @@ def lib_path():
 
 def _declare(lib):
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
-    lib.qb_plan_create.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(vp)]
+    sz = ctypes.c_size_t
+    lib.qb_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), i32]
+    lib.qb_workspace_bytes.restype = sz
+    lib.qb_plan_create.argtypes = [ctypes.POINTER(_Problem), i32, vp, sz, ctypes.POINTER(vp)]
     lib.qb_plan_create.restype = i32
+    lib.qb_plan_chunk_cells.argtypes = [vp]
+    lib.qb_plan_chunk_cells.restype = i32
+    lib.qb_adjoint_workspace_bytes.argtypes = [vp]
+    lib.qb_adjoint_workspace_bytes.restype = sz
+    lib.qb_batch_workspace_bytes.argtypes = [ctypes.POINTER(_Problem), i32]
+    lib.qb_batch_workspace_bytes.restype = sz
     lib.qb_plan_destroy.argtypes = [vp]
     lib.qb_plan_destroy.restype = i32
     lib.qb_plan_bytes.argtypes = [vp]
@@ -128,7 +144,7 @@ def _declare(lib):
     lib.qb_probe_fma.restype = i32
     lib.qb_probe_copy.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(dbl), vp]
     lib.qb_probe_copy.restype = i32
-    lib.qb_plan_enable_adjoint.argtypes = [vp]
+    lib.qb_plan_enable_adjoint.argtypes = [vp, vp, ctypes.c_size_t]
     lib.qb_plan_enable_adjoint.restype = i32
     lib.qb_collision_vjp.argtypes = [vp, vp, vp, vp, i32, vp]
     lib.qb_collision_vjp.restype = i32
@@ -154,7 +170,7 @@ def _declare(lib):
     lib.qb_plan_set_scheme.argtypes = [vp, i32, i32]
     lib.qb_plan_set_scheme.restype = i32
     lib.qb_plan_set_pairing.restype = i32
-    lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, ctypes.POINTER(vp)]
+    lib.qb_batch_create.argtypes = [ctypes.POINTER(_Problem), i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
     lib.qb_batch_create.restype = i32
     lib.qb_batch_destroy.argtypes = [vp]
     lib.qb_batch_destroy.restype = i32
@@ -261,31 +277,67 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _dev(t, dtype, shape, name):
+    """Check one device buffer before its pointer reaches the library: a
+    contiguous CUDA tensor of `dtype` and exactly `shape` (None entries match
+    any size).  A host tensor would hand a host pointer to a kernel; a
+    non-contiguous view would be read or written in the wrong order."""
+    if not hasattr(t, "is_cuda") or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if len(t.shape) != len(shape) or any(e is not None and int(a) != e for a, e in zip(t.shape, shape)):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return _ptr(t)
+
+
+def _workspace(nbytes):
+    """A device workspace of `nbytes` bytes (torch memory, 256-byte aligned)."""
+    import torch
+
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device="cuda")
+
+
 class Plan:
     """A qb_plan: quadrature tables and device buffers for one problem."""
 
-    def __init__(self, problem):
+    def __init__(self, problem, max_cells=0, adjoint=False):
+        """max_cells: cells per collision launch (0: min(Nx, 512)); adjoint:
+        lay out the reverse-mode workspace too (else enable_adjoint())."""
         import torch
 
         self.lib = load()
         self.problem = problem
         self.cdtype = torch.complex128 if problem.precision == "f64" else torch.complex64
-        h = ctypes.c_void_p()
         pc = problem._c()
-        _check(self.lib.qb_plan_create(ctypes.byref(pc), ctypes.byref(h)), "qb_plan_create")
+        nbytes = self.lib.qb_workspace_bytes(ctypes.byref(pc), int(max_cells))
+        if nbytes == 0:
+            _check(QB_EINVAL, "qb_workspace_bytes")
+        self.ws = _workspace(nbytes)
+        self.ws_adj = None
+        h = ctypes.c_void_p()
+        _check(self.lib.qb_plan_create(ctypes.byref(pc), int(max_cells), _ptr(self.ws), self.ws.numel(),
+                                       ctypes.byref(h)), "qb_plan_create")
         self.handle = h
+        if adjoint:
+            self.enable_adjoint()
 
     @property
     def nbytes(self):
         return self.lib.qb_plan_bytes(self.handle)
 
+    @property
+    def chunk_cells(self):
+        return self.lib.qb_plan_chunk_cells(self.handle)
+
     def _check_state(self, W, ncells=None):
         p = self.problem
         n = p.Nx if ncells is None else ncells
-        if not W.is_cuda or not W.is_contiguous() or W.dtype != self.cdtype:
-            raise ValueError(f"expected a contiguous CUDA {self.cdtype} tensor")
-        if tuple(W.shape[1:]) != (p.N, p.N, 2, 2) or W.shape[0] < n:
-            raise ValueError(f"expected shape [{n}, {p.N}, {p.N}, 2, 2], got {tuple(W.shape)}")
+        _dev(W, self.cdtype, (None, p.N, p.N, 2, 2), "state")
+        if W.shape[0] < n:
+            raise ValueError(f"expected at least {n} cells, got {W.shape[0]}")
 
     def collision(self, W, C=None, ncells=None):
         """qb_collision: C[W] for the first `ncells` cells of W."""
@@ -314,21 +366,13 @@ class Plan:
 
         self._check_state(W)
         p = self.problem
-        bp = ctypes.c_void_p(0)
-        if B is not None:
-            if B.dtype != torch.float64 or not B.is_cuda or tuple(B.shape) != (p.Nx, 3) or not B.is_contiguous():
-                raise ValueError("B must be a contiguous CUDA float64 tensor [Nx, 3]")
-            bp = _ptr(B)
+        bp = self._field(B)
         mp = ctypes.c_void_p(0)
         if moments is not None:
-            if moments.dtype != torch.float64 or tuple(moments.shape) != (nsteps + 1, p.Nx, 7):
-                raise ValueError("moments must be CUDA float64 [nsteps + 1, Nx, 7]")
-            mp = _ptr(moments)
+            mp = _dev(moments, torch.float64, (nsteps + 1, p.Nx, 7), "moments")
         if inflow is not None:
-            if inflow.dtype != torch.float64 or not inflow.is_cuda or tuple(inflow.shape) != (nsteps, 7) \
-                    or not inflow.is_contiguous():
-                raise ValueError("inflow must be a contiguous CUDA float64 tensor [nsteps, 7]")
-            _check(self.lib.qb_step_fluxes(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _ptr(inflow),
+            ip = _dev(inflow, torch.float64, (nsteps, 7), "inflow")
+            _check(self.lib.qb_step_fluxes(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, ip,
                                            _stream()), "qb_step_fluxes")
             return W
         _check(self.lib.qb_step(self.handle, _ptr(W), bp, float(dt), int(nsteps), mp, _stream()), "qb_step")
@@ -337,17 +381,20 @@ class Plan:
     def _field(self, B):
         import torch
 
-        p = self.problem
         if B is None:
             return ctypes.c_void_p(0)
-        if B.dtype != torch.float64 or not B.is_cuda or tuple(B.shape) != (p.Nx, 3) or not B.is_contiguous():
-            raise ValueError("B must be a contiguous CUDA float64 tensor [Nx, 3]")
-        return _ptr(B)
+        return _dev(B, torch.float64, (self.problem.Nx, 3), "B")
 
     # ------------------------------------------------------------ reverse mode
     def enable_adjoint(self):
-        """qb_plan_enable_adjoint: allocate the adjoint workspace (once)."""
-        _check(self.lib.qb_plan_enable_adjoint(self.handle), "qb_plan_enable_adjoint")
+        """qb_plan_enable_adjoint: lay out the reverse-mode buffers in a
+        workspace of qb_adjoint_workspace_bytes (once)."""
+        if self.ws_adj is not None:
+            return
+        nbytes = self.lib.qb_adjoint_workspace_bytes(self.handle)
+        ws = _workspace(nbytes)
+        _check(self.lib.qb_plan_enable_adjoint(self.handle, _ptr(ws), ws.numel()), "qb_plan_enable_adjoint")
+        self.ws_adj = ws
 
     def collision_vjp(self, W, lam, G=None, ncells=None):
         """qb_collision_vjp: G = C'(W)^T lam (torch's complex-gradient convention)."""
@@ -388,10 +435,13 @@ class Plan:
 
     def step_trace(self, W, B, dt, nsteps, trace):
         """qb_step_trace: nsteps steps in place, one record per step in `trace`."""
+        import torch
+
         self._check_state(W)
-        if trace.numel() < nsteps * self.trace_bytes or not trace.is_cuda:
+        tp = _dev(trace, torch.uint8, (None,), "trace")
+        if trace.numel() < nsteps * self.trace_bytes:
             raise ValueError("trace too small")
-        _check(self.lib.qb_step_trace(self.handle, _ptr(W), self._field(B), float(dt), int(nsteps), _ptr(trace),
+        _check(self.lib.qb_step_trace(self.handle, _ptr(W), self._field(B), float(dt), int(nsteps), tp,
                                       _stream()), "qb_step_trace")
         return W
 
@@ -408,12 +458,12 @@ class Plan:
         if W is not None:
             self._check_state(W)
             wp = _ptr(W)
-        rp = ctypes.c_void_p(0) if record is None else _ptr(record)
+        rp = ctypes.c_void_p(0)
+        if record is not None:
+            rp = _dev(record, torch.uint8, (self.trace_bytes,), "record")
         gp = ctypes.c_void_p(0)
         if gB is not None:
-            if gB.dtype != torch.float64 or tuple(gB.shape) != (self.problem.Nx, 3) or not gB.is_contiguous():
-                raise ValueError("gB must be a contiguous CUDA float64 tensor [Nx, 3]")
-            gp = _ptr(gB)
+            gp = _dev(gB, torch.float64, (self.problem.Nx, 3), "gB")
         _check(self.lib.qb_adjoint_step(self.handle, wp, rp, self._field(B), float(dt), _ptr(lam_next), _ptr(lam),
                                         gp, _stream()), "qb_adjoint_step")
         return lam
@@ -436,9 +486,8 @@ class Plan:
             gp = BC("dirichlet", inv_kT, mu_up, mu_down, U)._c().state
         if out is None:
             out = torch.empty((self.problem.Nx, QB_DIAG_FIELDS), dtype=torch.float64, device=W.device)
-        elif out.dtype != torch.float64 or tuple(out.shape) != (self.problem.Nx, QB_DIAG_FIELDS) or not out.is_contiguous():
-            raise ValueError("out must be a contiguous CUDA float64 tensor [Nx, QB_DIAG_FIELDS]")
-        _check(self.lib.qb_diagnostics(self.handle, _ptr(W), cp, None if gp is None else ctypes.byref(gp), _ptr(out),
+        op = _dev(out, torch.float64, (self.problem.Nx, QB_DIAG_FIELDS), "out")
+        _check(self.lib.qb_diagnostics(self.handle, _ptr(W), cp, None if gp is None else ctypes.byref(gp), op,
                                        _stream()), "qb_diagnostics")
         return out
 
@@ -449,7 +498,8 @@ class Plan:
         self._check_state(W)
         if out is None:
             out = torch.empty((self.problem.Nx, 7), dtype=torch.float64, device=W.device)
-        _check(self.lib.qb_moments(self.handle, _ptr(W), _ptr(out), _stream()), "qb_moments")
+        op = _dev(out, torch.float64, (self.problem.Nx, 7), "out")
+        _check(self.lib.qb_moments(self.handle, _ptr(W), op, _stream()), "qb_moments")
         return out
 
     # ------------------------------------------------------------ tiles
@@ -550,8 +600,13 @@ class Batch:
         self.lib = load()
         self.problems = list(problems)
         arr = (_Problem * len(self.problems))(*[p._c() for p in self.problems])
+        nbytes = self.lib.qb_batch_workspace_bytes(arr, len(self.problems))
+        if nbytes == 0:
+            _check(QB_EINVAL, "qb_batch_workspace_bytes")
+        self.ws = _workspace(nbytes)
         h = ctypes.c_void_p()
-        _check(self.lib.qb_batch_create(arr, len(self.problems), ctypes.byref(h)), "qb_batch_create")
+        _check(self.lib.qb_batch_create(arr, len(self.problems), _ptr(self.ws), self.ws.numel(), ctypes.byref(h)),
+               "qb_batch_create")
         self.handle = h
         prec = {p.precision for p in self.problems}
         self.cdtype = torch.complex128 if prec == {"f64"} else torch.complex64
@@ -570,26 +625,20 @@ class Batch:
         n = len(self.problems)
         if len(Ws) != n:
             raise ValueError("one state per problem")
-        for W, p in zip(Ws, self.problems):
-            if not W.is_cuda or not W.is_contiguous() or W.dtype != self.cdtype:
-                raise ValueError(f"expected contiguous CUDA {self.cdtype} tensors")
-            if tuple(W.shape) != (p.Nx, p.N, p.N, 2, 2):
-                raise ValueError(f"expected shape [{p.Nx}, {p.N}, {p.N}, 2, 2], got {tuple(W.shape)}")
         vp = ctypes.c_void_p
-        Wp = (vp * n)(*[W.data_ptr() for W in Ws])
+        Wp = (vp * n)(*[_dev(W, self.cdtype, (p.Nx, p.N, p.N, 2, 2), "state").value for W, p in zip(Ws, self.problems)])
         Bp = None
         if Bs is not None:
-            for B, p in zip(Bs, self.problems):
-                if B is not None and (B.dtype != torch.float64 or tuple(B.shape) != (p.Nx, 3)
-                                      or not B.is_contiguous()):
-                    raise ValueError("B entries must be contiguous CUDA float64 [Nx, 3] tensors or None")
-            Bp = (vp * n)(*[0 if B is None else B.data_ptr() for B in Bs])
+            if len(Bs) != n:
+                raise ValueError("one field (or None) per problem")
+            Bp = (vp * n)(*[0 if B is None else _dev(B, torch.float64, (p.Nx, 3), "B").value
+                            for B, p in zip(Bs, self.problems)])
         Mp = None
         if moments is not None:
-            for m, p in zip(moments, self.problems):
-                if m is not None and (m.dtype != torch.float64 or tuple(m.shape) != (nsteps + 1, p.Nx, 7)):
-                    raise ValueError("moments entries must be CUDA float64 [nsteps + 1, Nx, 7] or None")
-            Mp = (vp * n)(*[0 if m is None else m.data_ptr() for m in moments])
+            if len(moments) != n:
+                raise ValueError("one moments array (or None) per problem")
+            Mp = (vp * n)(*[0 if m is None else _dev(m, torch.float64, (nsteps + 1, p.Nx, 7), "moments").value
+                            for m, p in zip(moments, self.problems)])
         _check(self.lib.qb_batch_step(self.handle, Wp, Bp, float(dt), int(nsteps), Mp,
                                       QB_BATCH_GRAPH if graph else 0, _stream()), "qb_batch_step")
         return Ws

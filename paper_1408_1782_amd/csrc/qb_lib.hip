@@ -26,6 +26,8 @@ bool hip_ok(hipError_t e, const char* what) {
   return false;
 }
 
+void set_error(const char* what) { g_last_error = what; }
+
 namespace {
 
 // ------------------------------------------------------------------ quadrature (host, float64)
@@ -85,6 +87,16 @@ constexpr bool paired_t() {
   return qb::I3Regs<T, P, E>::PAIR;
 }
 
+// Tile shapes (elements per thread E; lanes per line P / E) compiled for
+// each padded grid size; the first is the default, qb_plan_tune picks one.
+std::vector<int> tile_candidates(int P) {
+  switch (P) {
+    case 32: return {16, 8};
+    case 64: return {16, 32};
+    default: return {16, 32};
+  }
+}
+
 // default node pairing of the I_3 kernel of this tile (register plan)
 bool i3_paired(int precision, int P, int E) {
   const bool d = precision == QB_F64;
@@ -107,12 +119,12 @@ int cfg_E(int precision, int P) {
 
 namespace {
 
+// copy a float64 host table, converted to T, into reserved device memory
 template <typename T>
-bool upload(qb_plan_s* pl, void** dst, const std::vector<double>& v) {
+bool put(void* dst, const std::vector<double>& v) {
   std::vector<T> h(v.size());
   for (size_t i = 0; i < v.size(); ++i) h[i] = (T)v[i];
-  if (!pl->alloc(dst, h.size() * sizeof(T))) return false;
-  return hip_ok(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return hip_ok(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
 }
 
 // col spec position of frequency indices (kx, ky) (FFT order)
@@ -125,13 +137,27 @@ inline size_t colspec_index(int kx, int ky, int E, int TPR, int NT) {
 
 inline int centered_h(int k, int P) { return k < P / 2 ? k : k - P; }
 
+// Reserve the workspace of one tile shape's table set (twiddles, phi',
+// K, psi, psi', weighted psi, psi' / P^2).
 template <typename T>
-bool build_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
+bool reserve_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
+  const size_t P = pl->P, J = pl->prob.J, FSZ = P * P, b = sizeof(T);
+  ts.E = E;
+  ts.built = false;
+  return pl->alloc(&ts.tw, 2 * P * b) && pl->alloc(&ts.phip, J * FSZ * b) && pl->alloc(&ts.Kt, J * FSZ * b) &&
+         pl->alloc(&ts.psi, J * FSZ * b) && pl->alloc(&ts.psip, J * FSZ * b) && pl->alloc(&ts.psiw, J * FSZ * b) &&
+         pl->alloc(&ts.psips, J * FSZ * b);
+}
+
+// Compute the table set of tile shape ts.E in float64 and copy it into its
+// reserved memory (Sec. 3.2: theta grids, phi_R, omega_G, psi_R).
+template <typename T>
+bool fill_layout_tables(qb_plan_s* pl, qb_plan_s::TabSet& ts) {
   const qb_problem& p = pl->prob;
+  const int E = ts.E;
   const int P = pl->P, TPR = P / E, NT = P * TPR, J = p.J;
   const double L = p.L, R = p.R;
   const size_t FSZ = (size_t)P * P;
-  ts.E = E;
   // (cos, sin)(2 pi q k / P) at [q][k], q < TPR, k < E  (engine twiddles)
   std::vector<double> tw(2 * P);
   for (int q = 0; q < TPR; ++q)
@@ -176,23 +202,19 @@ bool build_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
       }
     }
   }
-  return upload<T>(pl, &ts.tw, tw) && upload<T>(pl, &ts.phip, phip) && upload<T>(pl, &ts.Kt, Kt) &&
-         upload<T>(pl, &ts.psi, psi) && upload<T>(pl, &ts.psip, psip) && upload<T>(pl, &ts.psiw, psiw) &&
-         upload<T>(pl, &ts.psips, psips);
+  ts.built = put<T>(ts.tw, tw) && put<T>(ts.phip, phip) && put<T>(ts.Kt, Kt) && put<T>(ts.psi, psi) &&
+             put<T>(ts.psip, psip) && put<T>(ts.psiw, psiw) && put<T>(ts.psips, psips);
+  return ts.built;
 }
 
-// Make tile shape E current: build its table set on first use.
+// Make tile shape E current: fill its reserved table set on first use.
 template <typename T>
 bool select_tile(qb_plan_s* pl, int E) {
   int idx = -1;
   for (size_t i = 0; i < pl->tabs.size(); ++i)
     if (pl->tabs[i].E == E) idx = (int)i;
-  if (idx < 0) {
-    qb_plan_s::TabSet ts;
-    if (!build_layout_tables<T>(pl, E, ts)) return false;
-    pl->tabs.push_back(ts);
-    idx = (int)pl->tabs.size() - 1;
-  }
+  if (idx < 0) return false;
+  if (!pl->tabs[idx].built && !fill_layout_tables<T>(pl, pl->tabs[idx])) return false;
   pl->cur_tab = idx;
   pl->E = E;
   pl->TPR = pl->P / E;
@@ -204,7 +226,14 @@ bool select_tile(qb_plan_s* pl, int E) {
 // Gauss-Legendre weights and the separable modulation phases of
 // eq. approxH-JM (natural frequency order, independent of the tile).
 template <typename T>
-bool build_phases(qb_plan_s* pl) {
+bool reserve_phases(qb_plan_s* pl) {
+  const size_t P = pl->P, J = pl->prob.J, M = pl->prob.M, b = sizeof(T);
+  return pl->alloc(&pl->phx, J * M * P * 2 * b) && pl->alloc(&pl->phy, J * M * P * 2 * b) &&
+         pl->alloc(&pl->wm, M * b);
+}
+
+template <typename T>
+bool fill_phases(qb_plan_s* pl) {
   const qb_problem& p = pl->prob;
   const int P = pl->P, J = p.J, M = p.M;
   const double L = p.L, R = p.R;
@@ -238,12 +267,25 @@ bool build_phases(qb_plan_s* pl) {
         phy[o + 1] = std::sin(ay);
       }
     }
-  return upload<T>(pl, &pl->phx, phx) && upload<T>(pl, &pl->phy, phy) && upload<T>(pl, &pl->wm, wm);
+  return put<T>(pl->phx, phx) && put<T>(pl->phy, phy) && put<T>(pl->wm, wm);
+}
+
+// Reserve the phases and one table set per compiled tile shape of the
+// plan's padded grid.
+template <typename T>
+bool reserve_tables(qb_plan_s* pl) {
+  if (!reserve_phases<T>(pl)) return false;
+  for (int E : tile_candidates(pl->P)) {
+    qb_plan_s::TabSet ts;
+    if (!reserve_layout_tables<T>(pl, E, ts)) return false;
+    pl->tabs.push_back(ts);
+  }
+  return true;
 }
 
 template <typename T>
-bool build_tables(qb_plan_s* pl) {
-  return build_phases<T>(pl) && select_tile<T>(pl, pl->E);
+bool fill_tables(qb_plan_s* pl) {
+  return fill_phases<T>(pl) && select_tile<T>(pl, pl->E);
 }
 
 // Pauli components of W_FD (eq. W_FermiDirac) on the velocity grid: [4][N][N]
@@ -279,11 +321,13 @@ void fd_pauli(const qb_fd& s, int N, double L, double* out) {
 }
 
 // Wall tables of problem p (Dirichlet Phi or Maxwell W_FD on the velocity
-// grid, the Maxwell normalization Z) in device memory owned by `owner`.
+// grid, the Maxwell normalization Z) carved from `owner`'s workspace: the
+// device memory is reserved in every mode, and filled when not measuring.
 template <typename T>
 bool build_bc_for(qb_plan_s* owner, const qb_problem& p, qb::BcDev& bl, qb::BcDev& br, void** bcw, double** flux) {
   const int N = p.N;
   const size_t per = (size_t)N * N;
+  if (!owner->alloc(bcw, 2 * 4 * per * sizeof(T)) || !owner->alloc((void**)flux, 2 * sizeof(double))) return false;
   std::vector<double> bw(2 * 4 * per, 0.0);
   const qb_bc* bcs[2] = {&p.left, &p.right};
   qb::BcDev* dv[2] = {&bl, &br};
@@ -293,7 +337,7 @@ bool build_bc_for(qb_plan_s* owner, const qb_problem& p, qb::BcDev& bl, qb::BcDe
     dv[wall]->kind = b.kind;
     dv[wall]->alpha = b.alpha;
     dv[wall]->Z = 1.0;
-    if (b.kind == QB_PERIODIC) continue;
+    if (b.kind == QB_PERIODIC || owner->measuring()) continue;
     double* o = bw.data() + wall * 4 * per;
     fd_pauli(b.state, N, p.L, o);
     if (b.kind == QB_MAXWELL) {
@@ -308,8 +352,8 @@ bool build_bc_for(qb_plan_s* owner, const qb_problem& p, qb::BcDev& bl, qb::BcDe
       dv[wall]->Z = h * h * Z;
     }
   }
-  if (!upload<T>(owner, bcw, bw)) return false;
-  return owner->alloc((void**)flux, 2 * sizeof(double)) && hip_ok(hipMemset(*flux, 0, 2 * sizeof(double)), "hipMemset");
+  if (owner->measuring()) return true;
+  return put<T>(*bcw, bw) && hip_ok(hipMemset(*flux, 0, 2 * sizeof(double)), "hipMemset");
 }
 
 template <typename T>
@@ -339,26 +383,17 @@ bool build_adjoint(qb_plan_s* pl) {
   const size_t st = (size_t)4 * p.Nx * p.N * p.N * b;
   void** states[] = {&pl->wn, &pl->wa, &pl->w1, &pl->wb, &pl->lb, &pl->ls, &pl->la, &pl->cg, &pl->g0};
   for (void** q : states)
-    if (!pl->alloc(q, st)) return false;
-  return pl->alloc(&pl->lamP, C * 4 * FSZ * b) && pl->alloc(&pl->acot, C * 16 * FSZ * b) &&
-         pl->alloc(&pl->gspec, C * 22 * FSZ * b) && pl->alloc(&pl->gf0, C * 7 * FSZ * b) &&
-         pl->alloc(&pl->tsb, C * 2 * qb::kTermsVjpTasks * FSZ * b) && pl->alloc(&pl->i3g, C * J * 8 * FSZ * b) &&
-         pl->alloc(&pl->i3sb, C * J * 4 * FSZ * b) && pl->alloc(&pl->gsum, C * 8 * FSZ * b) &&
-         pl->alloc(&pl->i3t, C * J * 4 * FSZ * b) && pl->alloc(&pl->lamh, C * 4 * FSZ * b) &&
-         pl->alloc(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
-         pl->alloc((void**)&pl->lflux, 2 * sizeof(double));
+    if (!pl->alloc_adj(q, st)) return false;
+  return pl->alloc_adj(&pl->lamP, C * 4 * FSZ * b) && pl->alloc_adj(&pl->acot, C * 16 * FSZ * b) &&
+         pl->alloc_adj(&pl->gspec, C * 22 * FSZ * b) && pl->alloc_adj(&pl->gf0, C * 7 * FSZ * b) &&
+         pl->alloc_adj(&pl->tsb, C * 2 * qb::kTermsVjpTasks * FSZ * b) &&
+         pl->alloc_adj(&pl->i3g, C * J * 8 * FSZ * b) && pl->alloc_adj(&pl->i3sb, C * J * 4 * FSZ * b) &&
+         pl->alloc_adj(&pl->gsum, C * 8 * FSZ * b) && pl->alloc_adj(&pl->i3t, C * J * 4 * FSZ * b) &&
+         pl->alloc_adj(&pl->lamh, C * 4 * FSZ * b) &&
+         pl->alloc_adj(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
+         pl->alloc_adj((void**)&pl->lflux, 2 * sizeof(double));
 }
 
-
-// Tile shapes (elements per thread E; lanes per line P / E) compiled for
-// each padded grid size; the first is the default, qb_plan_tune picks one.
-std::vector<int> tile_candidates(int P) {
-  switch (P) {
-    case 32: return {16, 8};
-    case 64: return {16, 32};
-    default: return {16, 32};
-  }
-}
 
 template <typename T>
 bool collision_chunk(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s) {
@@ -881,28 +916,61 @@ qb_status validate(const qb_problem* p) {
   return QB_OK;
 }
 
-// Largest number of cells one collision launch covers: the workspace
-// (about (41 + 8 J) P^2 scalars per cell) is sized for this many.
+// Default number of cells one collision launch covers: the collision
+// workspace (about (43 + 12 J) P^2 scalars per cell) is sized for this many.
 constexpr int kChunkCells = 512;
 
-qb_plan_s* create_plan(const qb_problem& problem) {
-  qb_plan_s* pl = new qb_plan_s();
+int chunk_cells(const qb_problem& p, int max_cells) {
+  return std::min(p.Nx, max_cells > 0 ? max_cells : kChunkCells);
+}
+
+void init_plan(qb_plan_s* pl, const qb_problem& problem, int max_cells) {
   pl->prob = problem;
   pl->P = 2 * problem.N;
   pl->E = cfg_E(problem.precision, pl->P);
   pl->TPR = pl->P / pl->E;
   pl->NT = pl->P * pl->TPR;
-  pl->wcells = std::min(problem.Nx, kChunkCells);
-  bool ok;
-  if (problem.precision == QB_F64)
-    ok = build_tables<double>(pl) && build_bc<double>(pl) && build_buffers<double>(pl);
-  else
-    ok = build_tables<float>(pl) && build_bc<float>(pl) && build_buffers<float>(pl);
-  if (!ok) {
+  pl->wcells = chunk_cells(problem, max_cells);
+}
+
+// Carve (and, unless measuring, fill) everything a plan holds: phases and
+// the table set of every tile shape, wall tables, collision and state
+// buffers.  The same code sizes the workspace (measuring) and builds it.
+template <typename T>
+bool layout_plan(qb_plan_s* pl) {
+  if (!reserve_tables<T>(pl) || !build_bc<T>(pl) || !build_buffers<T>(pl)) return false;
+  return pl->measuring() || fill_tables<T>(pl);
+}
+
+bool layout_any(qb_plan_s* pl) {
+  return pl->prob.precision == QB_F64 ? layout_plan<double>(pl) : layout_plan<float>(pl);
+}
+
+size_t plan_workspace_bytes(const qb_problem& problem, int max_cells) {
+  qb_plan_s pl;
+  init_plan(&pl, problem, max_cells);
+  pl.ws.reset(nullptr, 0, true);
+  return layout_any(&pl) ? pl.ws.used : 0;
+}
+
+qb_plan_s* create_plan(const qb_problem& problem, int max_cells, void* ws, size_t ws_bytes) {
+  qb_plan_s* pl = new qb_plan_s();
+  init_plan(pl, problem, max_cells);
+  pl->ws.reset(ws, ws_bytes, false);
+  if (!layout_any(pl)) {
     delete pl;
     return nullptr;
   }
   return pl;
+}
+
+size_t adjoint_workspace_bytes(qb_plan_s* pl) {
+  const Arena keep = pl->adj;
+  pl->adj.reset(nullptr, 0, true);
+  const bool ok = pl->prob.precision == QB_F64 ? build_adjoint<double>(pl) : build_adjoint<float>(pl);
+  const size_t n = pl->adj.used;
+  pl->adj = keep;
+  return ok ? n : 0;
 }
 
 }  // namespace
@@ -919,20 +987,15 @@ struct qb_batch_s {
     std::vector<int> members;
     std::vector<Segment> segs;
     int total = 0;
-    double* B = nullptr;    // [total][3]
-    double* mom = nullptr;  // [mom_cap][total][7]
-    int mom_cap = 0;
+    double* B = nullptr;  // [total][3]
   };
   std::vector<Group> groups;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<uintptr_t> key;
-  size_t bytes() const {
-    size_t b = 0;
-    for (const Group& g : groups) b += g.plan->bytes;
-    return b;
-  }
+  size_t ws_used = 0;
+  size_t bytes() const { return ws_used; }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -961,17 +1024,29 @@ bool batch_enqueue(qb_batch_s* b, void* const* W, const double* const* B, double
     T* tmp = (T*)pl->st2;
     T* w1 = (T*)pl->st1;
     T* c = (T*)pl->cbuf;
-    bool any_mom = false;
     for (size_t k = 0; k < g.members.size(); ++k) {
       const int m = g.members[k];
       const Segment& sg = g.segs[k];
       if (!to_state<T, T>(pl, W[m], cur + (size_t)sg.offset * per, sg.Nx, s)) return false;
       hipLaunchKernelGGL(qb::k_copy_f64, dim3(blocks((size_t)sg.Nx * 3, 256)), dim3(256), 0, s, B ? B[m] : nullptr,
                          g.B + (size_t)sg.offset * 3, sg.Nx * 3);
-      any_mom = any_mom || (mom && mom[m]);
     }
-    const size_t mstride = (size_t)ntot * 7;
-    if (any_mom && !moments<T>(pl, cur, g.mom, s)) return false;
+    // moments snapshot `snap` of every problem that asked for them, written
+    // into its own array (component stride: the group's cell count)
+    auto snap_moments = [&](const T* state, int snap) {
+      if (!mom) return true;
+      const int id = pl->begin(QB_K_MOMENTS, s);
+      for (size_t k = 0; k < g.members.size(); ++k) {
+        const int m = g.members[k];
+        const Segment& sg = g.segs[k];
+        if (!mom[m]) continue;
+        hipLaunchKernelGGL((qb::k_moments<T>), dim3(sg.Nx), dim3(256), 0, s, state + (size_t)sg.offset * per,
+                           mom[m] + (size_t)snap * sg.Nx * 7, ntot, N, pl->prob.L);
+      }
+      pl->end(id, s);
+      return hip_ok(hipGetLastError(), "moments launch");
+    };
+    if (!snap_moments(cur, 0)) return false;
     auto half = [&](T*& a, T*& t) {
       const int id = pl->begin(QB_K_TRANSPORT, s);
       for (const Segment& sg : g.segs) transport_seg<T>(pl, a, t, 0.5 * dt, sg, ntot, s);
@@ -990,41 +1065,90 @@ bool batch_enqueue(qb_batch_s* b, void* const* W, const double* const* B, double
       hipLaunchKernelGGL((qb::k_heun<T>), dim3(blocks(n, 256)), dim3(256), 0, s, cur, w1, c, g.B, (T)dt, ntot, N, 2);
       pl->end(id, s);
       if (!half(cur, tmp)) return false;
-      if (any_mom && !moments<T>(pl, cur, g.mom + (it + 1) * mstride, s)) return false;
+      if (!snap_moments(cur, it + 1)) return false;
     }
     for (size_t k = 0; k < g.members.size(); ++k) {
       const int m = g.members[k];
       const Segment& sg = g.segs[k];
       if (!from_state<T, T>(pl, cur + (size_t)sg.offset * per, W[m], sg.Nx, s)) return false;
-      if (mom && mom[m])
-        hipLaunchKernelGGL(qb::k_scatter_moments, dim3(blocks((size_t)(nsteps + 1) * sg.Nx * 7, 256)), dim3(256), 0,
-                           s, (const double*)g.mom, mom[m], nsteps + 1, ntot, sg.offset, sg.Nx);
     }
     if (!hip_ok(hipGetLastError(), "batch launch")) return false;
   }
   return true;
 }
 
+// One group of a batch: its plan over all of the group's cells (periodic
+// placeholder walls), each member's wall tables and the group's field
+// array, carved from the group plan's workspace.
 template <typename T>
-qb_status batch_build(qb_batch_s* b) {
+bool group_layout(qb_batch_s* b, qb_batch_s::Group& g) {
+  qb_plan_s* pl = g.plan;
+  if (!layout_plan<T>(pl)) return false;
+  g.segs.clear();
+  int off = 0;
+  for (int m : g.members) {
+    const qb_problem& p = b->probs[m];
+    Segment sg{off, p.Nx, {}, {}, nullptr, nullptr, p.left.kind == QB_MAXWELL, p.right.kind == QB_MAXWELL};
+    void* bcw = nullptr;
+    if (!build_bc_for<T>(pl, p, sg.bl, sg.br, &bcw, &sg.flux)) return false;
+    sg.bcw = bcw;
+    g.segs.push_back(sg);
+    off += p.Nx;
+  }
+  return pl->alloc((void**)&g.B, (size_t)g.total * 3 * sizeof(double));
+}
+
+qb_problem group_problem(const qb_batch_s* b, const qb_batch_s::Group& g) {
+  qb_problem gp = b->probs[g.members[0]];
+  gp.Nx = g.total;
+  gp.left.kind = QB_PERIODIC;
+  gp.right.kind = QB_PERIODIC;
+  return gp;
+}
+
+// Lay out every group in [ws, ws + ws_bytes) (measuring when ws is null):
+// group k's plan workspace starts at a 256-byte boundary after group k-1's.
+qb_status batch_layout(qb_batch_s* b, void* ws, size_t ws_bytes) {
+  const bool measure = ws == nullptr;
+  size_t off = 0;
   for (qb_batch_s::Group& g : b->groups) {
-    qb_problem gp = b->probs[g.members[0]];
-    gp.Nx = g.total;
-    gp.left.kind = QB_PERIODIC;
-    gp.right.kind = QB_PERIODIC;
-    g.plan = create_plan(gp);
-    if (!g.plan) return QB_EHIP;
-    int off = 0;
-    for (int m : g.members) {
-      const qb_problem& p = b->probs[m];
-      Segment sg{off, p.Nx, {}, {}, nullptr, nullptr, p.left.kind == QB_MAXWELL, p.right.kind == QB_MAXWELL};
-      void* bcw = nullptr;
-      if (!build_bc_for<T>(g.plan, p, sg.bl, sg.br, &bcw, &sg.flux)) return QB_EHIP;
-      sg.bcw = bcw;
-      g.segs.push_back(sg);
-      off += p.Nx;
+    off = (off + 255) & ~(size_t)255;
+    qb_plan_s* pl = new qb_plan_s();
+    init_plan(pl, group_problem(b, g), 0);
+    pl->ws.reset(measure ? nullptr : (char*)ws + off, measure ? 0 : (off < ws_bytes ? ws_bytes - off : 0), measure);
+    g.plan = pl;
+    const bool ok = b->precision == QB_F64 ? group_layout<double>(b, g) : group_layout<float>(b, g);
+    if (!ok) return measure ? QB_EHIP : QB_EWORKSPACE;
+    off += pl->ws.used;
+  }
+  b->ws_used = off;
+  return QB_OK;
+}
+
+// Validate a batch description and group its problems by N.
+qb_status batch_groups(const qb_problem* problems, int nprob, qb_batch_s* b) {
+  const qb_problem& p0 = problems[0];
+  for (int i = 0; i < nprob; ++i) {
+    const qb_problem& p = problems[i];
+    const qb_status st = validate(&p);
+    if (st != QB_OK) return st;
+    if (p.precision != p0.precision || p.J != p0.J || p.L != p0.L || p.R != p0.R) return QB_EINVAL;
+  }
+  b->precision = p0.precision;
+  b->probs.assign(problems, problems + nprob);
+  for (int i = 0; i < nprob; ++i) {
+    const qb_problem& p = problems[i];
+    qb_batch_s::Group* g = nullptr;
+    for (auto& x : b->groups)
+      if (b->probs[x.members[0]].N == p.N) g = &x;
+    if (!g) {
+      b->groups.emplace_back();
+      g = &b->groups.back();
+    } else if (b->probs[g->members[0]].M != p.M) {
+      return QB_EINVAL;
     }
-    if (!g.plan->alloc((void**)&g.B, (size_t)g.total * 3 * sizeof(double))) return QB_EHIP;
+    g->members.push_back(i);
+    g->total += p.Nx;
   }
   return QB_OK;
 }
@@ -1034,12 +1158,20 @@ qb_status batch_build(qb_batch_s* b) {
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
-qb_status qb_plan_create(const qb_problem* problem, qb_plan* out) {
+size_t qb_workspace_bytes(const qb_problem* problem, int32_t max_cells) {
+  if (validate(problem) != QB_OK || max_cells < 0) return 0;
+  return plan_workspace_bytes(*problem, max_cells);
+}
+
+qb_status qb_plan_create(const qb_problem* problem, int32_t max_cells, void* workspace, size_t ws_bytes,
+                         qb_plan* out) {
   if (!out) return QB_EINVAL;
   *out = nullptr;
   qb_status st = validate(problem);
   if (st != QB_OK) return st;
-  qb_plan_s* pl = create_plan(*problem);
+  if (max_cells < 0 || !workspace) return QB_EINVAL;
+  if (ws_bytes < plan_workspace_bytes(*problem, max_cells)) return QB_EWORKSPACE;
+  qb_plan_s* pl = create_plan(*problem, max_cells, workspace, ws_bytes);
   if (!pl) return QB_EHIP;
   *out = pl;
   return QB_OK;
@@ -1052,7 +1184,9 @@ qb_status qb_plan_destroy(qb_plan plan) {
   return QB_OK;
 }
 
-size_t qb_plan_bytes(qb_plan plan) { return plan ? plan->bytes : 0; }
+size_t qb_plan_bytes(qb_plan plan) { return plan ? plan->bytes() : 0; }
+
+int32_t qb_plan_chunk_cells(qb_plan plan) { return plan ? plan->wcells : 0; }
 
 qb_status qb_collision(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream) {
   if (!plan || !W || !C || W == C) return QB_EINVAL;
@@ -1100,11 +1234,16 @@ qb_status qb_step_fluxes(qb_plan plan, void* W, const double* B, double dt, int3
   return do_step<float>(plan, W, B, dt, nsteps, moments_out, nullptr, s, inflow);
 }
 
-qb_status qb_plan_enable_adjoint(qb_plan plan) {
+size_t qb_adjoint_workspace_bytes(qb_plan plan) { return plan ? adjoint_workspace_bytes(plan) : 0; }
+
+qb_status qb_plan_enable_adjoint(qb_plan plan, void* workspace, size_t ws_bytes) {
   if (!plan) return QB_EINVAL;
   if (plan->adjoint) return QB_OK;
+  if (!workspace) return QB_EINVAL;
+  if (ws_bytes < adjoint_workspace_bytes(plan)) return QB_EWORKSPACE;
+  plan->adj.reset(workspace, ws_bytes, false);
   const bool ok = plan->prob.precision == QB_F64 ? build_adjoint<double>(plan) : build_adjoint<float>(plan);
-  if (!ok) return QB_EHIP;
+  if (!ok) return QB_EWORKSPACE;
   plan->adjoint = true;
   return QB_OK;
 }
@@ -1289,35 +1428,24 @@ qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream
   return st;
 }
 
-qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, qb_batch* out) {
+size_t qb_batch_workspace_bytes(const qb_problem* problems, int32_t nprob) {
+  if (!problems || nprob < 1) return 0;
+  qb_batch_s b;
+  if (batch_groups(problems, nprob, &b) != QB_OK || batch_layout(&b, nullptr, 0) != QB_OK) return 0;
+  return b.ws_used;
+}
+
+qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, void* workspace, size_t ws_bytes,
+                          qb_batch* out) {
   if (!out || !problems || nprob < 1) return QB_EINVAL;
   *out = nullptr;
-  const qb_problem& p0 = problems[0];
-  for (int i = 0; i < nprob; ++i) {
-    const qb_problem& p = problems[i];
-    const qb_status st = validate(&p);
-    if (st != QB_OK) return st;
-    if (p.precision != p0.precision || p.J != p0.J || p.L != p0.L || p.R != p0.R) return QB_EINVAL;
-  }
   qb_batch_s* b = new qb_batch_s();
-  b->precision = p0.precision;
-  b->probs.assign(problems, problems + nprob);
-  for (int i = 0; i < nprob; ++i) {
-    const qb_problem& p = problems[i];
-    qb_batch_s::Group* g = nullptr;
-    for (auto& x : b->groups)
-      if (b->probs[x.members[0]].N == p.N) g = &x;
-    if (!g) {
-      b->groups.emplace_back();
-      g = &b->groups.back();
-    } else if (b->probs[g->members[0]].M != p.M) {
-      delete b;
-      return QB_EINVAL;
-    }
-    g->members.push_back(i);
-    g->total += p.Nx;
-  }
-  const qb_status st = b->precision == QB_F64 ? batch_build<double>(b) : batch_build<float>(b);
+  qb_status st = batch_groups(problems, nprob, b);
+  if (st == QB_OK && !workspace) st = QB_EINVAL;
+  if (st == QB_OK && ws_bytes < qb_batch_workspace_bytes(problems, nprob)) st = QB_EWORKSPACE;
+  if (st == QB_OK) st = batch_layout(b, workspace, ws_bytes);
+  if (st == QB_OK && !hip_ok(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "hipStreamCreate"))
+    st = QB_EHIP;
   if (st != QB_OK) {
     delete b;
     return st;
@@ -1354,16 +1482,6 @@ qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, 
     if (!W[m]) return QB_EINVAL;
     if (0.5 * dt * p.L * p.Nx > 1.0 + 1e-12) return QB_ECFL;
   }
-  bool any_mom = false;
-  for (int m = 0; moments && m < np; ++m) any_mom = any_mom || moments[m];
-  // moments scratch (grows outside any capture)
-  for (auto& g : batch->groups) {
-    if (any_mom && nsteps + 1 > g.mom_cap) {
-      if (!g.plan->alloc((void**)&g.mom, (size_t)(nsteps + 1) * g.total * 7 * sizeof(double))) return QB_EHIP;
-      g.mom_cap = nsteps + 1;
-      batch->drop_graph();
-    }
-  }
   hipStream_t s = (hipStream_t)stream;
   auto run = [&](hipStream_t q) {
     return batch->precision == QB_F64 ? batch_enqueue<double>(batch, W, B, dt, nsteps, moments, q)
@@ -1383,8 +1501,6 @@ qb_status qb_batch_step(qb_batch batch, void* const* W, const double* const* B, 
   key.push_back((uintptr_t)nsteps);
   if (!batch->exec || key != batch->key) {
     batch->drop_graph();
-    if (!batch->cap && !hip_ok(hipStreamCreateWithFlags(&batch->cap, hipStreamNonBlocking), "hipStreamCreate"))
-      return QB_EHIP;
     std::vector<bool> prof;
     for (auto& g : batch->groups) {
       prof.push_back(g.plan->profiling);

@@ -15,11 +15,38 @@ using qb::DevPlan;
 
 // Records the text of a failed HIP call for qb_last_error(); true on success.
 bool hip_ok(hipError_t e, const char* what);
+// Records a message for qb_last_error().
+void set_error(const char* what);
+
+// Bump allocator over caller-owned device memory: the library never
+// allocates device memory itself.  In measuring mode it only adds up the
+// aligned sizes (the pointers stay null), which is how the workspace size
+// of a problem is computed from the same layout code that carves it.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  bool measure = true;
+  void reset(void* b, size_t c, bool m) {
+    base = (char*)b;
+    cap = c;
+    used = 0;
+    measure = m;
+  }
+  bool take(void** p, size_t n) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    if (!measure && off + n > cap) return false;
+    *p = measure ? nullptr : base + off;
+    used = off + n;
+    return true;
+  }
+};
 
 inline int blocks(size_t n, int b) { return (int)((n + b - 1) / b); }
 
 struct qb_plan_s {
   qb_problem prob;
+  Arena ws;   // the plan's workspace (tables, walls, collision and state buffers)
+  Arena adj;  // the reverse-mode workspace (qb_plan_enable_adjoint)
   int P, E, NT, TPR;
   int wcells;  // cells per collision launch (the workspace holds this many)
   bool i3_pair = true;  // I_3 kernel pairs the Gauss-Legendre nodes (tuned; default per tile)
@@ -27,12 +54,11 @@ struct qb_plan_s {
   int term_sel = 3;     // collision terms assembled: 1 C_c, 2 C_d, 3 both
   int limiter = 0;      // transport slope limiter: 0 minmod, 1 superbee, 2 MC, 3 van Leer
   int field_mode = 0;   // field term: 0 inside the Heun step, 1 exact rotation split around it
-  size_t bytes = 0;
-  std::vector<void*> allocs;
   // quadrature tables in the FFT engine's element order, one set per tile
   // shape E (elements per thread) that has been selected on this plan
   struct TabSet {
     int E = 0;
+    bool built = false;
     void *tw = nullptr, *phip = nullptr, *Kt = nullptr, *psi = nullptr, *psip = nullptr, *psiw = nullptr,
          *psips = nullptr;
   };
@@ -59,19 +85,25 @@ struct qb_plan_s {
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
 
+  bool measuring() const { return ws.measure; }
+  // carve n bytes of the plan workspace (false once it is exhausted)
   bool alloc(void** p, size_t n) {
-    if (!hip_ok(hipMalloc(p, n), "hipMalloc")) return false;
-    allocs.push_back(*p);
-    bytes += n;
-    return true;
+    if (ws.take(p, n)) return true;
+    set_error("plan workspace exhausted");
+    return false;
   }
+  bool alloc_adj(void** p, size_t n) {
+    if (adj.take(p, n)) return true;
+    set_error("adjoint workspace exhausted");
+    return false;
+  }
+  size_t bytes() const { return ws.used + (adjoint ? adj.used : 0); }
   ~qb_plan_s() {
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-    for (void* p : allocs) (void)hipFree(p);
   }
   hipEvent_t event() {
     if (!pool.empty()) {

@@ -35,11 +35,16 @@ def test_version_and_strerror():
         assert lib.qb_strerror(s)
 
 
+# a stand-in workspace address: every call below returns before the device
+# is touched, so the library never dereferences it
+FAKE_WS = ctypes.c_void_p(1 << 40)
+
+
 def _create(**kw):
     lib = qb.load()
     p = qb.Problem(**{**dict(Nx=4, N=16, J=8, M=8), **kw})._c()
     h = ctypes.c_void_p()
-    st = lib.qb_plan_create(ctypes.byref(p), ctypes.byref(h))
+    st = lib.qb_plan_create(ctypes.byref(p), 0, FAKE_WS, 1 << 40, ctypes.byref(h))
     return st, h
 
 
@@ -70,8 +75,12 @@ def test_null_arguments_rejected():
     lib = qb.load()
     assert lib.qb_collision(None, None, None, 1, None) == _lib.QB_EINVAL
     assert lib.qb_step(None, None, None, 1e-3, 1, None, None) == _lib.QB_EINVAL
-    assert lib.qb_plan_create(None, None) == _lib.QB_EINVAL
-    assert lib.qb_plan_enable_adjoint(None) == _lib.QB_EINVAL
+    assert lib.qb_plan_create(None, 0, None, 0, None) == _lib.QB_EINVAL
+    assert lib.qb_plan_enable_adjoint(None, None, 0) == _lib.QB_EINVAL
+    assert lib.qb_adjoint_workspace_bytes(None) == 0
+    assert lib.qb_batch_create(None, 0, None, 0, None) == _lib.QB_EINVAL
+    assert lib.qb_batch_workspace_bytes(None, 0) == 0
+    assert lib.qb_plan_chunk_cells(None) == 0
     assert lib.qb_collision_vjp(None, None, None, None, 1, None) == _lib.QB_EINVAL
     assert lib.qb_transport_vjp(None, None, 1e-3, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_step_trace(None, None, None, 1e-3, 1, None, None) == _lib.QB_EINVAL
@@ -83,3 +92,66 @@ def test_null_arguments_rejected():
     assert lib.qb_probe_fma(0, 1, None, None, None) == _lib.QB_EINVAL
     assert lib.qb_probe_copy(None, None, 16, 1, None, None) == _lib.QB_EINVAL
     assert lib.qb_step_fluxes(None, None, None, 1e-3, 1, None, None, None) == _lib.QB_EINVAL
+
+
+# ---------------------------------------------------------------- workspaces
+def _problem(**kw):
+    return qb.Problem(**{**dict(Nx=4, N=16, J=8, M=8), **kw})._c()
+
+
+def test_workspace_bytes_on_host():
+    """qb_workspace_bytes is host arithmetic: positive for valid problems,
+    0 for invalid ones, growing with the cell count per launch and the grid."""
+    lib = qb.load()
+    small = lib.qb_workspace_bytes(ctypes.byref(_problem()), 0)
+    assert small > 0
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem(N=24)), 0) == 0
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem()), -1) == 0
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem()), 1) < small        # one cell per launch
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem()), 4) == small       # default: min(Nx, 512)
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem()), 100) == small     # clamped to Nx
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem(N=32)), 0) > small
+    assert lib.qb_workspace_bytes(ctypes.byref(_problem(precision="f32")), 0) < small
+    probs = (_lib._Problem * 2)(_problem(), _problem(Nx=6, N=32, M=8))
+    assert lib.qb_batch_workspace_bytes(probs, 2) > lib.qb_workspace_bytes(ctypes.byref(_problem(N=32, Nx=6)), 0)
+    mixed = (_lib._Problem * 2)(_problem(), _problem(precision="f32"))
+    assert lib.qb_batch_workspace_bytes(mixed, 2) == 0
+
+
+def test_short_workspace_rejected_on_host():
+    """A workspace one byte short is refused with QB_EWORKSPACE before any
+    HIP call (the check is host arithmetic), for plans and batches."""
+    lib = qb.load()
+    p = _problem()
+    need = lib.qb_workspace_bytes(ctypes.byref(p), 0)
+    h = ctypes.c_void_p()
+    assert lib.qb_plan_create(ctypes.byref(p), 0, FAKE_WS, need - 1, ctypes.byref(h)) == _lib.QB_EWORKSPACE
+    assert not h.value
+    assert lib.qb_plan_create(ctypes.byref(p), 0, None, need, ctypes.byref(h)) == _lib.QB_EINVAL
+    assert lib.qb_plan_create(ctypes.byref(p), -2, FAKE_WS, need, ctypes.byref(h)) == _lib.QB_EINVAL
+    probs = (_lib._Problem * 2)(_problem(), _problem(Nx=6, N=32, M=8))
+    bneed = lib.qb_batch_workspace_bytes(probs, 2)
+    b = ctypes.c_void_p()
+    assert lib.qb_batch_create(probs, 2, FAKE_WS, bneed - 1, ctypes.byref(b)) == _lib.QB_EWORKSPACE
+    assert not b.value
+
+
+def _undefined_symbols(path):
+    """Dynamic symbols the library imports (nm -D --undefined-only)."""
+    import shutil
+    import subprocess
+
+    if shutil.which("nm"):
+        out = subprocess.run(["nm", "-D", "--undefined-only", path], capture_output=True, text=True, check=True)
+        return {line.split()[-1].split("@")[0] for line in out.stdout.splitlines() if line.strip()}
+    raise RuntimeError("nm not found")
+
+
+def test_library_imports_no_device_allocator():
+    """No entry point can allocate device memory: libqb.so imports none of
+    HIP's allocation or free routines (its memory is the caller's)."""
+    names = _undefined_symbols(_lib.lib_path())
+    assert "hipLaunchKernel" in names or any(n.startswith("hip") for n in names)
+    banned = {n for n in names if re.match(r"hip(Ext)?(Malloc|Free|HostAlloc|HostMalloc|MallocManaged|"
+                                           r"MallocAsync|MallocPitch|Malloc3D|MallocArray|FreeAsync|MemPool)", n)}
+    assert not banned, sorted(banned)
