@@ -11,7 +11,8 @@ Each output is an .npz next to this script:
   c2_reduced.npz      configuration 2 recipe on 8 cells (N = 32, J = 32,
                       M = 32, B = (0, 0, 0.5), dt = 1e-3): 2 steps.
   c3_cells.npz        configuration 3 (N = 64, J = 32, M = 64): C[W] of the
-                      initial state at 3 sampled cells.
+                      initial state at 8 sampled cells (both wall cells,
+                      their neighbours and four interior cells).
   c5_reduced_grad.npz configuration 5 recipe on a reduced instance (Nx = 8,
                       N = 16, J = M = 8, 20 steps, dt = 1e-3, B = (0, 0, 0.5),
                       periodic): the final state, the observable
@@ -71,7 +72,7 @@ def make_c2():
     np.savez_compressed(os.path.join(HERE, "c2_reduced.npz"), states=states, moments=moms)
 
 
-C3_CELLS = (0, 101, 255)
+C3_CELLS = (0, 1, 37, 101, 128, 200, 254, 255)
 
 
 def make_c3():

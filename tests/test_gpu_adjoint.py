@@ -174,8 +174,7 @@ def test_evolve_gradient_matches_oracle_reduced_configuration5(every):
     import torch
     import paper_1408_1782_amd as qb
     p = os.path.join(GOLDEN, "c5_reduced_grad.npz")
-    if not os.path.exists(p):
-        pytest.skip("c5_reduced_grad.npz not generated (python tests/golden/make_golden.py c5)")
+    assert os.path.exists(p), "c5_reduced_grad.npz missing (python tests/golden/make_golden.py c5)"
     g = np.load(p)
     w = wl.config(5, Nx=8, N=16)
     plan = make_plan(w, "f64", 8, 8)

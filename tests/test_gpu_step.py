@@ -66,6 +66,65 @@ def test_transport_matches_oracle(cfg, precision):
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_transport_full_slab_matches_oracle(precision):
+    """Configuration 3 at full size (256 cells, N = 64, Dirichlet left wall,
+    Maxwell right wall): 20 transport steps of the half step length the
+    splitting step uses (eq. slopeLimiterStep with the Sec. 2 walls),
+    element by element against the oracle."""
+    import torch
+    w = wl.config(3)
+    plan = make_plan(w, precision, J=4, M=4)
+    Wd = to_dev(w.W0, precision)
+    s = pauli.to_pauli(w.W0)
+    bl, br = bc_dict(w.left, w.N, w.L), bc_dict(w.right, w.N, w.L)
+    for _ in range(20):
+        plan.transport_step(Wd, 0.5 * w.dt)
+        s = tp.transport_step(s, 0.5 * w.dt, bl, br, w.L)
+    torch.cuda.synchronize()
+    got = pauli.to_pauli(Wd.cpu().numpy().astype(np.complex128))
+    assert rel(got, s) < TOL[precision]
+    # the walls moved the wall cells: the comparison covers the ghost rules
+    assert rel(s[[0, -1]], pauli.to_pauli(w.W0)[[0, -1]]) > 1e-4
+    plan.close()
+
+
+def test_binding_rejects_bad_buffers_before_the_library():
+    """Every device buffer is checked (CUDA, contiguous, dtype, shape)
+    before its pointer reaches the library: a host tensor or a transposed
+    view raises ValueError and nothing runs."""
+    import torch
+    w = wl.config(2, Nx=4, N=16)
+    plan = make_plan(w, "f64", J=4, M=4)
+    Wd = to_dev(w.W0, "f64")
+    W0 = Wd.clone()
+    bad_states = [Wd.cpu(), Wd.transpose(1, 2), Wd.to(torch.complex64), Wd[:, :8]]
+    for bad in bad_states:
+        with pytest.raises(ValueError):
+            plan.collision(bad)
+        with pytest.raises(ValueError):
+            plan.step(bad, None, w.dt, 1)
+    B = torch.zeros((w.Nx, 3), dtype=torch.float64, device="cuda")
+    for badB in (B.cpu(), torch.zeros((3, w.Nx), dtype=torch.float64, device="cuda").t(), B.float()):
+        with pytest.raises(ValueError):
+            plan.step(Wd, badB, w.dt, 1)
+    mom = torch.zeros((2, w.Nx, 7), dtype=torch.float64, device="cuda")
+    for badm in (mom.cpu(), torch.zeros((2, 7, w.Nx), dtype=torch.float64, device="cuda").transpose(1, 2)):
+        with pytest.raises(ValueError):
+            plan.step(Wd, B, w.dt, 1, moments=badm)
+        with pytest.raises(ValueError):
+            plan.moments(Wd, out=badm[0])
+    with pytest.raises(ValueError):
+        plan.step(Wd, B, w.dt, 1, inflow=torch.zeros((1, 7), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        plan.adjoint_step(Wd, None, w.dt, W=Wd, gB=B.cpu())
+    with pytest.raises(ValueError):
+        plan.diagnostics(Wd, out=torch.zeros((w.Nx, 11), dtype=torch.float64))
+    torch.cuda.synchronize()
+    assert torch.equal(Wd, W0)          # nothing ran
+    plan.close()
+
+
 def test_transport_rejects_cfl_violation():
     import paper_1408_1782_amd as qb
     w = wl.config(2, Nx=16, N=16)
@@ -119,8 +178,9 @@ def test_moments_match_oracle():
 
 def _golden(name):
     p = os.path.join(GOLDEN, name)
-    if not os.path.exists(p):
-        pytest.skip(f"{name} not generated (python tests/golden/make_golden.py)")
+    # a missing file is a failure, not a skip: the stored oracle values are
+    # part of the test (regenerate with python tests/golden/make_golden.py)
+    assert os.path.exists(p), f"{name} missing (python tests/golden/make_golden.py)"
     return np.load(p)
 
 
