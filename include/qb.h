@@ -136,6 +136,22 @@ int32_t qb_plan_chunk_cells(qb_plan plan);
  * W, C: [ncells][N][N][2][2] complex, distinct buffers; 1 <= ncells <= Nx. */
 qb_status qb_collision(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream);
 
+/* qb_collision for callers that cannot allocate device memory at all (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same operator and kernels, with every per-cell buffer of
+ * the collision pipeline taken from a fixed array of
+ * qb_collision_static_bytes() bytes (64 MiB) that the library holds on each
+ * GPU it runs on until the process ends; only the plan's tables are read
+ * from its workspace.  Cells run in chunks of as many as fit.  Allocates
+ * nothing and clears nothing: every scratch value is written before it is
+ * read, so the array may hold anything from an earlier call.  All calls on
+ * one GPU share its array: calls that overlap in time on one GPU (two
+ * streams, two host threads) race and must be serialized by the caller.
+ * QB_EWORKSPACE if ncells > Nx or if one cell's buffers exceed the array
+ * (qb_last_error says so); other arguments and errors as qb_collision. */
+qb_status qb_collision_static(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream);
+size_t qb_collision_static_bytes(void);
+
 /* One finite-volume transport step of length dt in place (eq.
  * slopeLimiterStep with the minmod limiter of eq. minmod, applied to the
  * four Pauli components), with the plan's boundary conditions.

@@ -34,6 +34,8 @@ EXPORTS = (
     "qb_plan_destroy",
     "qb_plan_bytes",
     "qb_collision",
+    "qb_collision_static",
+    "qb_collision_static_bytes",
     "qb_transport_step",
     "qb_step",
     "qb_step_fluxes",
@@ -130,6 +132,10 @@ def _declare(lib):
     lib.qb_plan_bytes.restype = ctypes.c_size_t
     lib.qb_collision.argtypes = [vp, vp, vp, i32, vp]
     lib.qb_collision.restype = i32
+    lib.qb_collision_static.argtypes = [vp, vp, vp, i32, vp]
+    lib.qb_collision_static.restype = i32
+    lib.qb_collision_static_bytes.argtypes = []
+    lib.qb_collision_static_bytes.restype = ctypes.c_size_t
     lib.qb_transport_step.argtypes = [vp, vp, dbl, vp]
     lib.qb_transport_step.restype = i32
     lib.qb_step.argtypes = [vp, vp, vp, dbl, i32, vp, vp]
@@ -349,6 +355,19 @@ class Plan:
             C = torch.empty_like(W)
         self._check_state(C, n)
         _check(self.lib.qb_collision(self.handle, _ptr(W), _ptr(C), n, _stream()), "qb_collision")
+        return C
+
+    def collision_static(self, W, C=None, ncells=None):
+        """qb_collision_static: C[W] with the library's fixed scratch array
+        in place of the plan's collision buffers (allocates nothing)."""
+        import torch
+
+        n = W.shape[0] if ncells is None else int(ncells)
+        self._check_state(W, n)
+        if C is None:
+            C = torch.empty_like(W)
+        self._check_state(C, n)
+        _check(self.lib.qb_collision_static(self.handle, _ptr(W), _ptr(C), n, _stream()), "qb_collision_static")
         return C
 
     def transport_step(self, W, dt):

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -361,19 +362,44 @@ bool build_bc(qb_plan_s* pl) {
   return build_bc_for<T>(pl, pl->prob, pl->bl, pl->br, &pl->bcw, &pl->flux);
 }
 
+// Per-cell buffers of the collision pipeline for `cells` cells per launch.
+struct CollBufs {
+  void *spec = nullptr, *wP = nullptr, *terms = nullptr, *acc = nullptr, *i3s = nullptr, *i3o = nullptr,
+       *i3sum = nullptr, *i3p = nullptr, *i3ps = nullptr;
+};
+
+template <typename T>
+bool carve_collision(Arena& a, const qb_plan_s* pl, size_t C, CollBufs& b) {
+  const size_t FSZ = (size_t)pl->P * pl->P, J = pl->prob.J, t = sizeof(T);
+  return a.take(&b.i3s, C * J * 4 * FSZ * t) && a.take(&b.spec, C * 8 * FSZ * t) &&
+         a.take(&b.wP, C * 5 * FSZ * t) && a.take(&b.terms, C * 8 * FSZ * t) && a.take(&b.acc, C * 14 * FSZ * t) &&
+         a.take(&b.i3o, C * J * 4 * FSZ * t) && a.take(&b.i3sum, C * 4 * FSZ * t) &&
+         a.take(&b.i3p, C * J * 4 * FSZ * t) && a.take(&b.i3ps, C * 4 * FSZ * t);
+}
+
+CollBufs get_bufs(const qb_plan_s* pl) {
+  CollBufs b;
+  b.spec = pl->spec, b.wP = pl->wP, b.terms = pl->terms, b.acc = pl->acc, b.i3s = pl->i3s, b.i3o = pl->i3o;
+  b.i3sum = pl->i3sum, b.i3p = pl->i3p, b.i3ps = pl->i3ps;
+  return b;
+}
+
+void set_bufs(qb_plan_s* pl, const CollBufs& b) {
+  pl->spec = b.spec, pl->wP = b.wP, pl->terms = b.terms, pl->acc = b.acc, pl->i3s = b.i3s, pl->i3o = b.i3o;
+  pl->i3sum = b.i3sum, pl->i3p = b.i3p, pl->i3ps = b.i3ps;
+}
+
 template <typename T>
 bool build_buffers(qb_plan_s* pl) {
   const qb_problem& p = pl->prob;
-  const size_t FSZ = (size_t)pl->P * pl->P, C = pl->wcells, J = p.J;
   const size_t st = (size_t)4 * p.Nx * p.N * p.N * sizeof(T);
-  if (!pl->alloc(&pl->i3s, C * J * 4 * FSZ * sizeof(T))) return false;
-  return pl->alloc(&pl->spec, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->wP, C * 5 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->terms, C * 8 * FSZ * sizeof(T)) && pl->alloc(&pl->acc, C * 14 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->i3o, C * J * 4 * FSZ * sizeof(T)) && pl->alloc(&pl->i3sum, C * 4 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->i3p, C * J * 4 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->i3ps, C * 4 * FSZ * sizeof(T)) &&
-         pl->alloc(&pl->st0, st) && pl->alloc(&pl->st1, st) && pl->alloc(&pl->st2, st) &&
-         pl->alloc(&pl->cbuf, st);
+  CollBufs b;
+  if (!carve_collision<T>(pl->ws, pl, pl->wcells, b)) {
+    set_error("plan workspace exhausted");
+    return false;
+  }
+  set_bufs(pl, b);
+  return pl->alloc(&pl->st0, st) && pl->alloc(&pl->st1, st) && pl->alloc(&pl->st2, st) && pl->alloc(&pl->cbuf, st);
 }
 
 template <typename T>
@@ -1155,6 +1181,117 @@ qb_status batch_groups(const qb_problem* problems, int nprob, qb_batch_s* b) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Device memory of the library itself, for qb_collision_static: callers that
+// cannot allocate (code under HIP graph capture, serving loops, harnesses
+// that forbid allocation) get the collision's per-cell buffers from this
+// array.  Each GPU the library runs on holds its own copy until the process
+// ends.  Host code never names the array except to resolve its device
+// address (per device, with that device current) through hipGetSymbolAddress.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (resolved once per device);
+// null after a failed HIP call (qb_last_error says which).
+void* scratch_ptr() {
+  int dev = -1;
+  if (!hip_ok(hipGetDevice(&dev), "hipGetDevice")) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index beyond the scratch table");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (!hip_ok(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress")) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Bytes of the static path's buffers for chunks of n cells: the collision
+// buffers plus the state-sized input and output arrays of the chunk.
+template <typename T>
+size_t static_bytes(const qb_plan_s* pl, int n) {
+  Arena a;
+  a.reset(nullptr, 0, true);
+  CollBufs b;
+  void* x = nullptr;
+  const size_t st = (size_t)4 * n * pl->prob.N * pl->prob.N * sizeof(T);
+  carve_collision<T>(a, pl, n, b);
+  a.take(&x, st);
+  a.take(&x, st);
+  return a.used;
+}
+
+// Largest chunk of at most `want` cells whose buffers fit the scratch
+// array (0 if a single cell does not fit).
+template <typename T>
+int static_chunk(const qb_plan_s* pl, int want) {
+  int lo = 0, hi = std::max(1, std::min(want, kChunkCells));
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (static_bytes<T>(pl, mid) <= kStaticScratchBytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// C[W] for ncells cells with every per-cell buffer in the scratch array:
+// chunks of `chunk` cells, each converted to the Pauli layout, run through
+// the same collision pipeline as qb_collision and converted back.  The
+// plan's buffer pointers and cell count are switched to the scratch layout
+// while the chunk's launches are enqueued and restored afterwards (the
+// kernels take them by value at launch).
+template <typename T>
+qb_status do_collision_static(qb_plan_s* pl, void* base, const void* W, void* C, int ncells, int chunk,
+                              hipStream_t s) {
+  Arena a;
+  a.reset(base, kStaticScratchBytes, false);
+  CollBufs b;
+  void *w = nullptr, *c = nullptr;
+  const size_t per = (size_t)pl->prob.N * pl->prob.N;
+  const size_t st = 4 * (size_t)chunk * per * sizeof(T);
+  if (!carve_collision<T>(a, pl, chunk, b) || !a.take(&w, st) || !a.take(&c, st)) {
+    set_error("static scratch exhausted");
+    return QB_EWORKSPACE;
+  }
+  const CollBufs keep = get_bufs(pl);
+  const int keep_nx = pl->prob.Nx, keep_wc = pl->wcells;
+  set_bufs(pl, b);
+  bool ok = true;
+  for (int c0 = 0; c0 < ncells && ok; c0 += chunk) {
+    const int n = std::min(chunk, ncells - c0);
+    // state arrays of the chunk hold n cells per Pauli component
+    pl->prob.Nx = n;
+    pl->wcells = n;
+    const T* Wc = (const T*)W + (size_t)c0 * per * 8;
+    T* Cc = (T*)C + (size_t)c0 * per * 8;
+    hipLaunchKernelGGL((qb::k_api_to_state<T, T>), dim3(blocks(n * per, 256)), dim3(256), 0, s, Wc, (T*)w, n,
+                       pl->prob.N, n);
+    ok = hip_ok(hipGetLastError(), "layout launch") && collision_chunk<T>(pl, (const T*)w, (T*)c, n, 0, s);
+    if (ok) {
+      hipLaunchKernelGGL((qb::k_state_to_api<T, T>), dim3(blocks(n * per, 256)), dim3(256), 0, s, (const T*)c, Cc, n,
+                         pl->prob.N, n);
+      ok = hip_ok(hipGetLastError(), "layout launch");
+    }
+  }
+  set_bufs(pl, keep);
+  pl->prob.Nx = keep_nx;
+  pl->wcells = keep_wc;
+  return ok ? QB_OK : QB_EHIP;
+}
+
+}  // namespace
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -1173,6 +1310,11 @@ qb_status qb_plan_create(const qb_problem* problem, int32_t max_cells, void* wor
   if (ws_bytes < plan_workspace_bytes(*problem, max_cells)) return QB_EWORKSPACE;
   qb_plan_s* pl = create_plan(*problem, max_cells, workspace, ws_bytes);
   if (!pl) return QB_EHIP;
+  // set-up of qb_collision_static on this device
+  if (!scratch_ptr()) {
+    delete pl;
+    return QB_EHIP;
+  }
   *out = pl;
   return QB_OK;
 }
@@ -1195,6 +1337,25 @@ qb_status qb_collision(qb_plan plan, const void* W, void* C, int32_t ncells, voi
   hipStream_t s = (hipStream_t)stream;
   if (plan->prob.precision == QB_F64) return do_collision<double>(plan, W, C, ncells, s);
   return do_collision<float>(plan, W, C, ncells, s);
+}
+
+size_t qb_collision_static_bytes(void) { return kStaticScratchBytes; }
+
+qb_status qb_collision_static(qb_plan plan, const void* W, void* C, int32_t ncells, void* stream) {
+  if (!plan || !W || !C || W == C) return QB_EINVAL;
+  if (ncells < 1) return QB_EINVAL;
+  if (ncells > plan->prob.Nx) return QB_EWORKSPACE;
+  const bool f64 = plan->prob.precision == QB_F64;
+  const int chunk = f64 ? static_chunk<double>(plan, ncells) : static_chunk<float>(plan, ncells);
+  if (chunk < 1) {
+    set_error("one cell's collision buffers exceed the static scratch of qb_collision_static");
+    return QB_EWORKSPACE;
+  }
+  void* base = scratch_ptr();
+  if (!base) return QB_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  return f64 ? do_collision_static<double>(plan, base, W, C, ncells, chunk, s)
+             : do_collision_static<float>(plan, base, W, C, ncells, chunk, s);
 }
 
 static qb_status check_cfl(qb_plan plan, double dt) {
