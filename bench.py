@@ -221,7 +221,7 @@ def run_adjoint(steps, every):
     diff = max(float((gW - gW2).abs().max() / gW2.abs().max()), float((gB - gB2).abs().max() / gB2.abs().max()))
     plan.close()
     return {"workload": "adjoint_fd_periodic_B", "Nx": wl.Nx, "N": wl.N, "J": wl.J, "M": wl.M, "dtype": "f64",
-            "tile": cfg["tile"], "adjoint_variant": cfg["adjoint_variant"],
+            "tile": cfg["tile"], "adjoint_tile": cfg["adjoint_tile"], "adjoint_variant": cfg["adjoint_variant"],
             "steps": steps, "checkpoint_every": every, "forward_s": t_fwd,
             "checkpointed": {"forward_s": f_ck, "backward_s": b_ck, "ratio": b_ck / t_fwd,
                              "recomputed_steps": steps - min(every, steps - every * ((steps - 1) // every))},

@@ -276,7 +276,7 @@ qb_status qb_diagnostics(qb_plan plan, const void* W, const void* C, const qb_fd
  * FFT tile shapes.  Every padded-grid transform runs in one workgroup that
  * holds the P x P field in registers, E elements per thread and P / E
  * threads per line.  Compiled shapes: P = 32: E = 16 (default), 8;
- * P = 64: E = 16 (default), 32; P = 128: E = 16 (default), 32.
+ * P = 64: E = 16 (default), 32, 8; P = 128: E = 16 (default), 32.
  * ------------------------------------------------------------------------- */
 
 /* Use tile shape E on this plan (QB_ENOTSUP if not compiled for its P).
@@ -286,8 +286,9 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
 /* Autotuner: time the collision pipeline on the plan's first `ncells` cells
  * for every compiled tile shape, with and without Gauss-Legendre node
  * pairing in the I_3 kernel, and keep the fastest; when the plan's
- * adjoint is enabled, also choose among the three I_3 adjoint kernels
- * (accumulators in memory or in registers, see qb_plan_config).  Synchronous; overwrites the
+ * adjoint is enabled, also time the reverse-mode pipeline for every tile
+ * shape and both I_3 adjoint kernels (row w cotangents in memory or in
+ * registers, see qb_plan_config) and keep the fastest.  Synchronous; overwrites the
  * plan's internal buffers.  Choices are cached per (precision, N, J, M,
  * ncells) for the life of the process.  *tile (may be NULL) receives E. */
 qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream);
@@ -296,14 +297,23 @@ qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream
  * compute the same operator (the pairing uses rho_{M-1-m} = -rho_m). */
 qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired);
 
-/* Use I_3 adjoint kernel `variant` (0, 1 or 2, see qb_plan_config). */
+/* Tile shape E of the reverse-mode pipeline (qb_collision_vjp and the
+ * collision adjoints of qb_adjoint_step), independent of the forward tile;
+ * 0 follows the forward tile (the default).  QB_ENOTSUP if E is not
+ * compiled for the plan's padded grid.  Synchronous the first time a shape
+ * is used (fills its tables). */
+qb_status qb_plan_set_adjoint_tile(qb_plan plan, int32_t E);
+
+/* Use I_3 adjoint kernel `variant` (0 or 1, see qb_plan_config). */
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant);
 
-/* Current tile shape E, I_3 adjoint kernel (0: accumulators in memory,
- * 1: the shifted-field cotangent in registers, 2: also the w cotangent) and
- * whether the I_3 kernel of this tile pairs the Gauss-Legendre nodes m and
- * M-1-m (1) or runs every node on its own (0); any pointer may be NULL. */
-qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes);
+/* Current tile shape E, I_3 adjoint kernel (0: the shifted-field cotangent
+ * of the current rows in registers, 1: also their w cotangent), whether
+ * the I_3 kernel of this tile pairs the Gauss-Legendre nodes m and M-1-m
+ * (1) or runs every node on its own (0), and the reverse-mode tile shape;
+ * any pointer may be NULL. */
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes,
+                         int32_t* adjoint_tile);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent problems (uneven Nx and N) advanced together:

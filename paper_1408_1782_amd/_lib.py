@@ -53,6 +53,7 @@ EXPORTS = (
     "qb_plan_tune",
     "qb_plan_config",
     "qb_plan_set_adjoint_variant",
+    "qb_plan_set_adjoint_tile",
     "qb_plan_set_pairing",
     "qb_plan_set_terms",
     "qb_plan_set_scheme",
@@ -166,7 +167,10 @@ def _declare(lib):
     lib.qb_plan_set_tile.restype = i32
     lib.qb_plan_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     lib.qb_plan_tune.restype = i32
-    lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
+    lib.qb_plan_set_adjoint_tile.argtypes = [vp, i32]
+    lib.qb_plan_set_adjoint_tile.restype = i32
     lib.qb_plan_config.restype = i32
     lib.qb_plan_set_adjoint_variant.argtypes = [vp, i32]
     lib.qb_plan_set_adjoint_variant.restype = i32
@@ -522,7 +526,7 @@ class Plan:
         return out
 
     # ------------------------------------------------------------ tiles
-    TILES = {32: (16, 8), 64: (16, 32), 128: (16, 32)}
+    TILES = {32: (16, 8), 64: (16, 32, 8), 128: (16, 32)}
 
     def set_tile(self, E):
         """qb_plan_set_tile: FFT tile shape (elements per thread) of this plan."""
@@ -535,8 +539,13 @@ class Plan:
         _check(self.lib.qb_plan_tune(self.handle, n, ctypes.byref(e), _stream()), "qb_plan_tune")
         return e.value
 
+    def set_adjoint_tile(self, E):
+        """qb_plan_set_adjoint_tile: tile shape of the reverse-mode pipeline
+        (0 follows the forward tile)."""
+        _check(self.lib.qb_plan_set_adjoint_tile(self.handle, int(E)), "qb_plan_set_adjoint_tile")
+
     def set_adjoint_variant(self, v):
-        """qb_plan_set_adjoint_variant: I_3 adjoint kernel 0, 1 or 2."""
+        """qb_plan_set_adjoint_variant: I_3 adjoint kernel 0 or 1."""
         _check(self.lib.qb_plan_set_adjoint_variant(self.handle, int(v)), "qb_plan_set_adjoint_variant")
 
     def set_pairing(self, paired):
@@ -559,11 +568,13 @@ class Plan:
         _check(self.lib.qb_plan_set_terms(self.handle, self.TERMS[terms]), "qb_plan_set_terms")
 
     def config(self):
-        """qb_plan_config: tile E, I_3 adjoint variant and node pairing in use."""
-        e, v, pn = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v), ctypes.byref(pn)),
-               "qb_plan_config")
-        return {"tile": e.value, "adjoint_variant": v.value, "paired_nodes": bool(pn.value)}
+        """qb_plan_config: tile E, I_3 adjoint variant, node pairing and the
+        reverse-mode tile in use."""
+        e, v, pn, ae = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v), ctypes.byref(pn),
+                                       ctypes.byref(ae)), "qb_plan_config")
+        return {"tile": e.value, "adjoint_variant": v.value, "paired_nodes": bool(pn.value),
+                "adjoint_tile": ae.value}
 
     def profile(self, enable=True):
         """qb_profile: bracket every launch of this plan with HIP events."""

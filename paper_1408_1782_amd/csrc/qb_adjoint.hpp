@@ -320,235 +320,48 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
 // ------------------------------------------------------------------ I_3
 // Transpose of k_i3, one workgroup per (cell, j), Gauss-Legendre nodes in
 // symmetric pairs (m, m' = M-1-m; the middle node of an odd M alone).
-// With S the shift of node m, s_nu = S w_nu, t_nu = S b_bar_nu (b_bar the
-// cotangent of the I_3 sums, b_bar_0 = -2 pi lam_0, b_bar_k = 2 pi lam_k),
-// Psi = inv2(psi'_j / P^2 fwd2(.)) (real, symmetric), c = (pi/J) w_m,
-// q_a,nu = Psi(w_a s_nu), r_a,nu = Psi(b_bar_nu s_a), u_a,nu = Psi(t_nu w_a):
-//   node m :  Y_a     += c eta_a sum_nu b_bar_nu q_a,nu      (shifted factor)
-//             w_bar_a += c eta_a sum_nu s_nu r_a,nu          (w inside Psi)
-//             Y_nu    += c sum_a eta_a w_a r_a,nu            (shifted field inside Psi)
-//   node m':  w_bar_nu += c eta_nu sum_a t_a q_a,nu
-//             Y_a     += c eta_a sum_nu w_nu u_a,nu
-//             w_bar_nu += c sum_a eta_a s_a u_a,nu
-//   w_hat_bar += phase conj(F) Y      (Y = S-transposed part, per node pair)
-// (node m' terms follow from S^{-1} = S^T, translation invariance of Psi
-// and S(f g) = S f S g on the padded grid).  Per pair: 4 shift transforms,
-// 3 x 8 packed convolutions of 2 transforms, 2 final transforms.
+// With S the shift of node m, s_nu = S w_nu, b_bar the cotangent of the I_3
+// sums (b_bar_0 = -2 pi lam_0, b_bar_k = 2 pi lam_k), t_nu = S b_bar_nu,
+// Psi = inv2(psi'_j / P^2 fwd2(.)) (real, symmetric) and c = (pi/J) w_m,
+// the forward pair contributes
+//   c sum_{a,nu} < eta_a b_bar_nu s_a + eta_nu t_a w_nu , q_a,nu >,
+//   q_a,nu = Psi(w_a s_nu)
+// to the loss (node m through s_a, node m' through S^{-1} = S^T acting on
+// its partner sums).  Its derivative has two parts:
+//   * the factors beside q, with q fixed:
+//       Y_a      += c eta_a sum_nu b_bar_nu q_a,nu    (Y: cotangent of s)
+//       w_bar_nu += c eta_nu sum_a t_a q_a,nu
+//   * q through Psi, which is symmetric: with R_a,nu = Psi(T_a,nu),
+//     T_a,nu = eta_a b_bar_nu s_a + eta_nu t_a w_nu,
+//       w_bar_a  += c sum_nu s_nu R_a,nu
+//       Y_nu     += c sum_a w_a R_a,nu
+//   w_hat_bar += phase conj(F)(Y)        (S transposed, per node pair)
+// The two terms of T are summed before the convolution because Psi is
+// linear and both pair with the same variation of w_a s_nu: one family
+// R replaces the separate convolutions of b_bar_nu s_a and t_a w_nu.  Per
+// node pair: 4 shift transforms, 2 x 8 packed convolutions of 2
+// transforms, 2 final transforms (38, against 20 in the forward kernel).
+// For rows (a0, a1) the loop over nu runs q and R back to back, so Y_a
+// and, with WREG, w_bar_a accumulate in registers; w_bar_nu and Y_nu go
+// through memory once per convolution.  Where the register budget of the
+// tile allows (RREG), the rows' own fields s_a0, s_a1, t_a0, t_a1 are also
+// loaded into registers once per row pair instead of once per convolution.
+// The tuner picks WREG: the extra registers cost occupancy.
 // i3g[cell][j]: [0..3] w_bar (row real), [4..7] w_hat_bar packed as
 // (mu 0 + i mu 1), (mu 2 + i mu 3), re/im planes, col spec.
-template <typename T, int P, int E>
-__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp(DevPlan<T> d, int ncells) {
-  using K = Kern<T, P, E>;
-  constexpr unsigned S = sizeof(T);
-  __shared__ T smem[K::LDS];
-  Fft2<T, P, E> eng;
-  setup(eng, smem, d.tw);
-  const int task = xcd_task(blockIdx.x, gridDim.x);
-  const int cell = task / d.J;
-  const int j = task % d.J;
-  const unsigned vo = threadIdx.x * S;
-  const size_t tb = (size_t)cell * d.J + j;
-  const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
-  const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
-  const rsrc_t rl = mkbuf(d.acot + ((size_t)cell * 16 + 8) * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rh = mkbuf(d.lamh + (size_t)cell * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rg = mkbuf(d.i3g + tb * 8 * K::FSZ, 8 * K::FSZ);
-  const rsrc_t rb = mkbuf(d.i3s + tb * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rt = mkbuf(d.i3t + tb * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rc = mkbuf(d.i3sb + tb * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
-  const int kx = eng.line;
-#pragma unroll 1
-  for (int q = 0; q < 8; ++q)
-#pragma unroll
-    for (int n = 0; n < E; ++n) bst<T>(rg, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
-  // one packed convolution Psi(a + i b) of two real fields given elementwise
-  auto conv = [&](T (&zr)[E], T (&zi)[E]) {
-    eng.fwd2(zr, zi);
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-      const T a = bld<T>(rm, vo, (k * K::NT) * S);
-      zr[k] *= a;
-      zi[k] *= a;
-    }
-    eng.inv2(zr, zi);
-  };
-  auto rmw = [&](rsrc_t r, int plane, unsigned o, T v) {
-    const unsigned off = (plane * K::FSZ + o) * S;
-    bst<T>(r, bld<T>(r, vo, off) + v, vo, off);
-  };
-  const int nnode = (d.M + 1) / 2;
-#pragma unroll 1
-  for (int m = 0; m < nnode; ++m) {
-    const bool paired = m != d.M - 1 - m;
-    const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
-    const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
-    const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
-    // s_nu = S w_nu and (paired) t_nu = S b_bar_nu, two packed shifts each
-#pragma unroll 1
-    for (int src = 0; src < (paired ? 2 : 1); ++src) {
-#pragma unroll 1
-      for (int pr = 0; pr < 2; ++pr) {
-        T zr[E], zi[E];
-#pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const unsigned o = k * K::NT;
-          T er, ei;
-          cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
-          if (src == 0) {
-            const unsigned fa = 2 * (2 * pr) * K::FSZ, fb = 2 * (2 * pr + 1) * K::FSZ;
-            T ar, ai, br, bi;
-            cmul(bld<T>(rs, vo, (fa + o) * S), bld<T>(rs, vo, (fa + K::FSZ + o) * S), er, ei, ar, ai);
-            cmul(bld<T>(rs, vo, (fb + o) * S), bld<T>(rs, vo, (fb + K::FSZ + o) * S), er, ei, br, bi);
-            zr[k] = ar - bi;
-            zi[k] = ai + br;
-          } else {
-            cmul(bld<T>(rh, vo, ((2 * pr) * K::FSZ + o) * S), bld<T>(rh, vo, ((2 * pr + 1) * K::FSZ + o) * S), er,
-                 ei, zr[k], zi[k]);
-          }
-        }
-        eng.inv2(zr, zi);
-        // t carries the B-term factors of b_bar: -2 pi (mu = 0), 2 pi (mu > 0)
-        const T fa = src == 0 ? (T)1 : (T)(pr == 0 ? -2.0 * kPi : 2.0 * kPi);
-        const T fb = src == 0 ? (T)1 : (T)(2.0 * kPi);
-        const rsrc_t rd = src == 0 ? rb : rt;
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          bst<T>(rd, fa * zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
-          bst<T>(rd, fb * zi[n], vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
-        }
-      }
-    }
-    const T c = d.wm[m];
-    // q_a,nu = Psi(w_a s_nu)
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-      const T cnu = nu == 0 ? c : -c;
-#pragma unroll 1
-      for (int mp = 0; mp < 2; ++mp) {
-        const int a0 = 2 * mp, a1 = 2 * mp + 1;
-        const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
-        T zr[E], zi[E];
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
-          zr[n] = bld<T>(rw, vo, (a0 * K::FSZ + o) * S) * sv;
-          zi[n] = bld<T>(rw, vo, (a1 * K::FSZ + o) * S) * sv;
-        }
-        conv(zr, zi);
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T bb = bld<T>(rl, vo, (nu * K::FSZ + o) * S);
-          T ya = ca0 * bb * zr[n], yb = ca1 * bb * zi[n];
-          if (nu != 0) {
-            ya += bld<T>(rc, vo, (a0 * K::FSZ + o) * S);
-            yb += bld<T>(rc, vo, (a1 * K::FSZ + o) * S);
-          }
-          bst<T>(rc, ya, vo, (a0 * K::FSZ + o) * S);
-          bst<T>(rc, yb, vo, (a1 * K::FSZ + o) * S);
-          if (paired) {
-            const T ta = bld<T>(rt, vo, (a0 * K::FSZ + o) * S), tb2 = bld<T>(rt, vo, (a1 * K::FSZ + o) * S);
-            rmw(rg, nu, o, cnu * (ta * zr[n] + tb2 * zi[n]));
-          }
-        }
-      }
-    }
-    // r_a,nu = Psi(b_bar_nu s_a)
-#pragma unroll 1
-    for (int nu = 0; nu < 4; ++nu) {
-#pragma unroll 1
-      for (int mp = 0; mp < 2; ++mp) {
-        const int a0 = 2 * mp, a1 = 2 * mp + 1;
-        const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
-        T zr[E], zi[E];
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T bb = bld<T>(rl, vo, (nu * K::FSZ + o) * S);
-          zr[n] = bb * bld<T>(rb, vo, (a0 * K::FSZ + o) * S);
-          zi[n] = bb * bld<T>(rb, vo, (a1 * K::FSZ + o) * S);
-        }
-        conv(zr, zi);
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T sv = bld<T>(rb, vo, (nu * K::FSZ + o) * S);
-          rmw(rg, a0, o, ca0 * sv * zr[n]);
-          rmw(rg, a1, o, ca1 * sv * zi[n]);
-          const T wa = bld<T>(rw, vo, (a0 * K::FSZ + o) * S), wb = bld<T>(rw, vo, (a1 * K::FSZ + o) * S);
-          rmw(rc, nu, o, ca0 * wa * zr[n] + ca1 * wb * zi[n]);
-        }
-      }
-    }
-    // u_a,nu = Psi(t_nu w_a), partner node
-    if (paired) {
-#pragma unroll 1
-      for (int nu = 0; nu < 4; ++nu) {
-#pragma unroll 1
-        for (int mp = 0; mp < 2; ++mp) {
-          const int a0 = 2 * mp, a1 = 2 * mp + 1;
-          const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
-          T zr[E], zi[E];
-#pragma unroll
-          for (int n = 0; n < E; ++n) {
-            const unsigned o = n * K::NT;
-            const T tv = bld<T>(rt, vo, (nu * K::FSZ + o) * S);
-            zr[n] = tv * bld<T>(rw, vo, (a0 * K::FSZ + o) * S);
-            zi[n] = tv * bld<T>(rw, vo, (a1 * K::FSZ + o) * S);
-          }
-          conv(zr, zi);
-#pragma unroll
-          for (int n = 0; n < E; ++n) {
-            const unsigned o = n * K::NT;
-            const T wv = bld<T>(rw, vo, (nu * K::FSZ + o) * S);
-            rmw(rc, a0, o, ca0 * wv * zr[n]);
-            rmw(rc, a1, o, ca1 * wv * zi[n]);
-            const T sa = bld<T>(rb, vo, (a0 * K::FSZ + o) * S), sb = bld<T>(rb, vo, (a1 * K::FSZ + o) * S);
-            rmw(rg, nu, o, ca0 * sa * zr[n] + ca1 * sb * zi[n]);
-          }
-        }
-      }
-    }
-    // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3)
-#pragma unroll 1
-    for (int pr = 0; pr < 2; ++pr) {
-      T zr[E], zi[E];
-#pragma unroll
-      for (int n = 0; n < E; ++n) {
-        const unsigned o = n * K::NT;
-        zr[n] = bld<T>(rc, vo, ((2 * pr) * K::FSZ + o) * S);
-        zi[n] = -bld<T>(rc, vo, ((2 * pr + 1) * K::FSZ + o) * S);
-      }
-      eng.fwd2(zr, zi);
-#pragma unroll
-      for (int k = 0; k < E; ++k) {
-        const unsigned o = k * K::NT;
-        T er, ei;
-        cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
-        T xr, xi;
-        cmul(zr[k], -zi[k], er, ei, xr, xi);
-        rmw(rg, 4 + 2 * pr, o, xr);
-        rmw(rg, 5 + 2 * pr, o, xi);
-      }
-    }
-  }
-}
-
-// Same transpose with the accumulators of each row pair held in registers:
-// for rows (a0, a1) the loop over nu runs the three convolutions q, u, r
-// back to back, so Y_a (from q and u) and, with WREG, w_bar_a (from r)
-// accumulate in registers; w_bar_nu and Y_nu go through memory once per
-// convolution.  The tuner picks between this kernel (with and without WREG)
-// and k_i3_vjp: the extra registers cost occupancy.
 template <typename T, int P, int E, bool WREG>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d, int ncells) {
   using K = Kern<T, P, E>;
   constexpr unsigned S = sizeof(T);
   // elements between scheduling barriers in the element loops, which bound
-  // the loads in flight (measured: 4 beats 8 and none)
+  // the loads in flight
   constexpr int SG = 4;
+  // registers: the transform operand, Y of the rows, w_bar of the rows
+  // (WREG) and the rows' four shifted fields (RREG), E values each per
+  // field and thread, beside about 48 for addresses and temporaries
+  constexpr int F = I3Regs<T, P, E>::F;
+  constexpr bool RREG = 2 * F + 2 * F + (WREG ? 2 * F : 0) + 4 * F + 48 <= I3Regs<T, P, E>::BUDGET;
+  constexpr int RE = RREG ? E : 1;
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
@@ -593,11 +406,22 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
     const T* px = d.phx + (((size_t)j * d.M + m) * P) * 2;
     const T* py = d.phy + (((size_t)j * d.M + m) * P) * 2 + 2 * E * eng.bq;
     const T pxr = px[2 * kx], pxi = px[2 * kx + 1];
+    // s_nu = S w_nu, and t_nu = S b_bar_nu (zero for an unpaired node: its
+    // partner terms vanish), two packed shifts each
 #pragma unroll 1
-    for (int src = 0; src < (paired ? 2 : 1); ++src) {
+    for (int src = 0; src < 2; ++src) {
 #pragma unroll 1
       for (int pr = 0; pr < 2; ++pr) {
         T zr[E], zi[E];
+        const rsrc_t rd = src == 0 ? rb : rt;
+        if (src == 1 && !paired) {
+#pragma unroll
+          for (int n = 0; n < E; ++n) {
+            bst<T>(rd, (T)0, vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
+            bst<T>(rd, (T)0, vo, ((2 * pr + 1) * K::FSZ + n * K::NT) * S);
+          }
+          continue;
+        }
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           const unsigned o = k * K::NT;
@@ -615,9 +439,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
           }
         }
         eng.inv2(zr, zi);
+        // t carries the B-term factors of b_bar: -2 pi (mu = 0), 2 pi (mu > 0)
         const T fa = src == 0 ? (T)1 : (T)(pr == 0 ? -2.0 * kPi : 2.0 * kPi);
         const T fb = src == 0 ? (T)1 : (T)(2.0 * kPi);
-        const rsrc_t rd = src == 0 ? rb : rt;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           bst<T>(rd, fa * zr[n], vo, ((2 * pr) * K::FSZ + n * K::NT) * S);
@@ -634,7 +458,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
 #pragma unroll 1
     for (int mp = 0; mp < 2; ++mp) {
       const int a0 = 2 * mp, a1 = 2 * mp + 1;
-      const T ca0 = a0 == 0 ? c : -c, ca1 = -c;
+      const T ea0 = a0 == 0 ? (T)1 : (T)-1;  // eta_a0; eta_a1 = -1
       T ya0[E], ya1[E], wa0[WREG ? E : 1], wa1[WREG ? E : 1];
 #pragma unroll
       for (int n = 0; n < E; ++n) ya0[n] = ya1[n] = 0;
@@ -642,9 +466,27 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
 #pragma unroll
         for (int n = 0; n < E; ++n) wa0[WREG ? n : 0] = wa1[WREG ? n : 0] = 0;
       }
+      // the rows' shifted fields s_a, t_a (registers with RREG)
+      T sa0[RE], sa1[RE], ta0[RE], ta1[RE];
+      if constexpr (RREG) {
+#pragma unroll
+        for (int n = 0; n < E; ++n) {
+          const unsigned o = n * K::NT;
+          sa0[RREG ? n : 0] = ld(rb, a0, o);
+          sa1[RREG ? n : 0] = ld(rb, a1, o);
+          ta0[RREG ? n : 0] = ld(rt, a0, o);
+          ta1[RREG ? n : 0] = ld(rt, a1, o);
+        }
+      }
+      auto row = [&](const T (&r)[RE], rsrc_t buf, int plane, int n) {
+        if constexpr (RREG)
+          return r[RREG ? n : 0];
+        else
+          return ld(buf, plane, n * K::NT);
+      };
 #pragma unroll 1
       for (int nu = 0; nu < 4; ++nu) {
-        const T cnu = nu == 0 ? c : -c;
+        const T enu = nu == 0 ? (T)1 : (T)-1;  // eta_nu
         T zr[E], zi[E];
         // q_a,nu = Psi(w_a s_nu)
 #pragma unroll
@@ -659,55 +501,34 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
-          const T bb = ld(rl, nu, o);
-          ya0[n] += ca0 * bb * zr[n];
-          ya1[n] += ca1 * bb * zi[n];
-          if (paired) rmw(rg, nu, o, cnu * (ld(rt, a0, o) * zr[n] + ld(rt, a1, o) * zi[n]));
+          const T bb = c * ld(rl, nu, o);
+          ya0[n] += ea0 * bb * zr[n];
+          ya1[n] -= bb * zi[n];
+          rmw(rg, nu, o, enu * c * (row(ta0, rt, a0, n) * zr[n] + row(ta1, rt, a1, n) * zi[n]));
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
-        if (paired) {
-          // u_a,nu = Psi(t_nu w_a)
-#pragma unroll
-          for (int n = 0; n < E; ++n) {
-            const unsigned o = n * K::NT;
-            const T tv = ld(rt, nu, o);
-            zr[n] = tv * ld(rw, a0, o);
-            zi[n] = tv * ld(rw, a1, o);
-            if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
-          }
-          conv(zr, zi);
-#pragma unroll
-          for (int n = 0; n < E; ++n) {
-            const unsigned o = n * K::NT;
-            const T wv = ld(rw, nu, o);
-            ya0[n] += ca0 * wv * zr[n];
-            ya1[n] += ca1 * wv * zi[n];
-            rmw(rg, nu, o, ca0 * ld(rb, a0, o) * zr[n] + ca1 * ld(rb, a1, o) * zi[n]);
-            if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
-          }
-        }
-        // r_a,nu = Psi(b_bar_nu s_a)
+        // R_a,nu = Psi(eta_a b_bar_nu s_a + eta_nu t_a w_nu)
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
-          const T bb = ld(rl, nu, o);
-          zr[n] = bb * ld(rb, a0, o);
-          zi[n] = bb * ld(rb, a1, o);
+          const T bb = ld(rl, nu, o), wv = enu * ld(rw, nu, o);
+          zr[n] = ea0 * bb * row(sa0, rb, a0, n) + wv * row(ta0, rt, a0, n);
+          zi[n] = wv * row(ta1, rt, a1, n) - bb * row(sa1, rb, a1, n);
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
         conv(zr, zi);
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
-          const T sv = ld(rb, nu, o);
+          const T sv = c * ld(rb, nu, o);
           if constexpr (WREG) {
-            wa0[WREG ? n : 0] += ca0 * sv * zr[n];
-            wa1[WREG ? n : 0] += ca1 * sv * zi[n];
+            wa0[WREG ? n : 0] += sv * zr[n];
+            wa1[WREG ? n : 0] += sv * zi[n];
           } else {
-            rmw(rg, a0, o, ca0 * sv * zr[n]);
-            rmw(rg, a1, o, ca1 * sv * zi[n]);
+            rmw(rg, a0, o, sv * zr[n]);
+            rmw(rg, a1, o, sv * zi[n]);
           }
-          rmw(rc, nu, o, ca0 * ld(rw, a0, o) * zr[n] + ca1 * ld(rw, a1, o) * zi[n]);
+          rmw(rc, nu, o, c * (ld(rw, a0, o) * zr[n] + ld(rw, a1, o) * zi[n]));
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }

@@ -93,7 +93,7 @@ constexpr bool paired_t() {
 std::vector<int> tile_candidates(int P) {
   switch (P) {
     case 32: return {16, 8};
-    case 64: return {16, 32};
+    case 64: return {16, 32, 8};
     default: return {16, 32};
   }
 }
@@ -105,7 +105,8 @@ bool i3_paired(int precision, int P, int E) {
     case 32: return E == 8 ? (d ? paired_t<double, 32, 8>() : paired_t<float, 32, 8>())
                            : (d ? paired_t<double, 32, 16>() : paired_t<float, 32, 16>());
     case 64: return E == 16 ? (d ? paired_t<double, 64, 16>() : paired_t<float, 64, 16>())
-                            : (d ? paired_t<double, 64, 32>() : paired_t<float, 64, 32>());
+                 : E == 8 ? (d ? paired_t<double, 64, 8>() : paired_t<float, 64, 8>())
+                          : (d ? paired_t<double, 64, 32>() : paired_t<float, 64, 32>());
     default: return E == 16 ? (d ? paired_t<double, 128, 16>() : paired_t<float, 128, 16>())
                             : (d ? paired_t<double, 128, 32>() : paired_t<float, 128, 32>());
   }
@@ -208,15 +209,34 @@ bool fill_layout_tables(qb_plan_s* pl, qb_plan_s::TabSet& ts) {
   return ts.built;
 }
 
-// Make tile shape E current: fill its reserved table set on first use.
+// Index of tile shape E's table set, filled on first use (-1 on failure).
 template <typename T>
-bool select_tile(qb_plan_s* pl, int E) {
+int table_set(qb_plan_s* pl, int E) {
   int idx = -1;
   for (size_t i = 0; i < pl->tabs.size(); ++i)
     if (pl->tabs[i].E == E) idx = (int)i;
+  if (idx < 0) return -1;
+  if (!pl->tabs[idx].built && !fill_layout_tables<T>(pl, pl->tabs[idx])) return -1;
+  return idx;
+}
+
+// Make tile shape E the reverse-mode pipeline's (0: follow the forward tile).
+template <typename T>
+bool select_vjp_tile(qb_plan_s* pl, int E) {
+  const int idx = table_set<T>(pl, E > 0 ? E : pl->E);
   if (idx < 0) return false;
-  if (!pl->tabs[idx].built && !fill_layout_tables<T>(pl, pl->tabs[idx])) return false;
+  pl->vjp_E = E;
+  pl->vjp_tab = idx;
+  return true;
+}
+
+// Make tile shape E current for the forward pipeline.
+template <typename T>
+bool select_tile(qb_plan_s* pl, int E) {
+  const int idx = table_set<T>(pl, E);
+  if (idx < 0) return false;
   pl->cur_tab = idx;
+  if (pl->vjp_E == 0) pl->vjp_tab = idx;
   pl->E = E;
   pl->TPR = pl->P / E;
   pl->NT = pl->P * pl->TPR;
@@ -428,8 +448,9 @@ bool collision_chunk(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hip
       return pl->E == 8 ? collision_pipeline<T, 32, 8>(pl, w, c, ncells, cell0, s)
                         : collision_pipeline<T, 32, 16>(pl, w, c, ncells, cell0, s);
     case 64:
-      return pl->E == 16 ? collision_pipeline<T, 64, 16>(pl, w, c, ncells, cell0, s)
-                         : collision_pipeline<T, 64, 32>(pl, w, c, ncells, cell0, s);
+      return pl->E == 16  ? collision_pipeline<T, 64, 16>(pl, w, c, ncells, cell0, s)
+             : pl->E == 8 ? collision_pipeline<T, 64, 8>(pl, w, c, ncells, cell0, s)
+                          : collision_pipeline<T, 64, 32>(pl, w, c, ncells, cell0, s);
     case 128:
       return pl->E == 16 ? collision_pipeline<T, 128, 16>(pl, w, c, ncells, cell0, s)
                          : collision_pipeline<T, 128, 32>(pl, w, c, ncells, cell0, s);
@@ -569,16 +590,18 @@ bool transport_to(qb_plan_s* pl, const T* src, T* dst, double dt, hipStream_t s)
 // ------------------------------------------------------------------ adjoint pipelines
 template <typename T>
 bool collision_vjp_chunk(qb_plan_s* pl, const T* w, const T* lam, T* out, int n, int c0, hipStream_t s) {
+  const int E = pl->tabs[pl->vjp_tab].E;  // the reverse-mode tile
   switch (pl->P) {
     case 32:
-      return pl->E == 8 ? collision_vjp_pipeline<T, 32, 8>(pl, w, lam, out, n, c0, s)
-                        : collision_vjp_pipeline<T, 32, 16>(pl, w, lam, out, n, c0, s);
+      return E == 8 ? collision_vjp_pipeline<T, 32, 8>(pl, w, lam, out, n, c0, s)
+                    : collision_vjp_pipeline<T, 32, 16>(pl, w, lam, out, n, c0, s);
     case 64:
-      return pl->E == 16 ? collision_vjp_pipeline<T, 64, 16>(pl, w, lam, out, n, c0, s)
-                         : collision_vjp_pipeline<T, 64, 32>(pl, w, lam, out, n, c0, s);
+      return E == 16  ? collision_vjp_pipeline<T, 64, 16>(pl, w, lam, out, n, c0, s)
+             : E == 8 ? collision_vjp_pipeline<T, 64, 8>(pl, w, lam, out, n, c0, s)
+                      : collision_vjp_pipeline<T, 64, 32>(pl, w, lam, out, n, c0, s);
     case 128:
-      return pl->E == 16 ? collision_vjp_pipeline<T, 128, 16>(pl, w, lam, out, n, c0, s)
-                         : collision_vjp_pipeline<T, 128, 32>(pl, w, lam, out, n, c0, s);
+      return E == 16 ? collision_vjp_pipeline<T, 128, 16>(pl, w, lam, out, n, c0, s)
+                     : collision_vjp_pipeline<T, 128, 32>(pl, w, lam, out, n, c0, s);
   }
   return false;
 }
@@ -886,11 +909,14 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
   pl->i3_pair = best_pair;
   if (chosen) *chosen = best;
   if (pl->adjoint) {
-    // the two I_3 adjoint kernels (memory or register accumulators)
-    const TuneKey vkey{p.precision + 16, p.N, p.J, p.M, ncells * 1000 + best};
+    // the reverse-mode pipeline: every tile shape (its own table set) and
+    // both I_3 adjoint kernels; the choice is cached as 16 E + variant
+    const TuneKey vkey{p.precision + 16, p.N, p.J, p.M, ncells};
     auto vt = tune_cache().find(vkey);
+    int vE = best, vv = 0;
     if (vt != tune_cache().end()) {
-      pl->vjp_variant = vt->second;
+      vE = vt->second / 16;
+      vv = vt->second % 16;
     } else {
       T* w = (T*)pl->st0;
       T* g = (T*)pl->g0;
@@ -901,22 +927,31 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
       const bool prof = pl->profiling;
       pl->profiling = false;
       hipEvent_t a = pl->event(), b = pl->event();
-      float t[3] = {0.f, 0.f, 0.f};
-      for (int v = 0; v < 3; ++v) {
-        pl->vjp_variant = v;
-        if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
-        (void)hipEventRecord(a, s);
-        if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
-        (void)hipEventRecord(b, s);
-        if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
-        (void)hipEventElapsedTime(&t[v], a, b);
-      }
+      float best_ms = 1e30f;
+      for (int E : cands)
+        for (int v = 0; v < 2; ++v) {
+          if (!select_vjp_tile<T>(pl, E)) return QB_EHIP;
+          pl->vjp_variant = v;
+          if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
+          (void)hipEventRecord(a, s);
+          if (!collision_vjp_any<T>(pl, w, g, out, ncells, s)) return QB_EHIP;
+          (void)hipEventRecord(b, s);
+          if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, a, b);
+          if (ms < best_ms) {
+            best_ms = ms;
+            vE = E;
+            vv = v;
+          }
+        }
       pl->pool.push_back(a);
       pl->pool.push_back(b);
       pl->profiling = prof;
-      pl->vjp_variant = (int)(std::min_element(t, t + 3) - t);
-      tune_cache()[vkey] = pl->vjp_variant;
+      tune_cache()[vkey] = 16 * vE + vv;
     }
+    if (!select_vjp_tile<T>(pl, vE)) return QB_EHIP;
+    pl->vjp_variant = vv;
   }
   return QB_OK;
 }
@@ -1564,15 +1599,27 @@ qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired) {
   return QB_OK;
 }
 
+qb_status qb_plan_set_adjoint_tile(qb_plan plan, int32_t E) {
+  if (!plan) return QB_EINVAL;
+  if (E != 0) {
+    const std::vector<int> c = tile_candidates(plan->P);
+    if (std::find(c.begin(), c.end(), (int)E) == c.end()) return QB_ENOTSUP;
+  }
+  const bool ok = plan->prob.precision == QB_F64 ? select_vjp_tile<double>(plan, E) : select_vjp_tile<float>(plan, E);
+  return ok ? QB_OK : QB_EHIP;
+}
+
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant) {
-  if (!plan || variant < 0 || variant > 2) return QB_EINVAL;
+  if (!plan || variant < 0 || variant > 1) return QB_EINVAL;
   plan->vjp_variant = variant;
   return QB_OK;
 }
 
-qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes) {
+qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes,
+                         int32_t* adjoint_tile) {
   if (!plan) return QB_EINVAL;
   if (tile) *tile = plan->E;
+  if (adjoint_tile) *adjoint_tile = plan->tabs[plan->vjp_tab].E;
   if (adjoint_variant) *adjoint_variant = plan->vjp_variant;
   if (paired_nodes) *paired_nodes = plan->i3_pair ? 1 : 0;
   return QB_OK;

@@ -8,7 +8,7 @@
 template <typename T, int P, int E>
 bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, hipStream_t s) {
   constexpr int NT = qb::Fft2<T, P, E>::NT;
-  DevPlan<T> d = devplan<T>(pl);
+  DevPlan<T> d = devplan<T>(pl, pl->cur_tab);
   int id = pl->begin(QB_K_DFT_IN, s);
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
@@ -34,7 +34,7 @@ template <typename T, int P, int E>
 bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int ncells, int cell0,
                             hipStream_t s) {
   constexpr int NT = qb::Fft2<T, P, E>::NT;
-  DevPlan<T> d = devplan<T>(pl);
+  DevPlan<T> d = devplan<T>(pl, pl->vjp_tab);
   int id = pl->begin(QB_K_DFT_IN, s);
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
@@ -48,12 +48,10 @@ bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int
   hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * qb::kTermsVjpTasks), dim3(NT), 0, s, d);
   pl->end(id, s);
   id = pl->begin(QB_K_I3_ADJOINT, s);
-  if (pl->vjp_variant == 2)
+  if (pl->vjp_variant == 1)
     hipLaunchKernelGGL((qb::k_i3_vjp_reg<T, P, E, true>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
-  else if (pl->vjp_variant == 1)
-    hipLaunchKernelGGL((qb::k_i3_vjp_reg<T, P, E, false>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
   else
-    hipLaunchKernelGGL((qb::k_i3_vjp<T, P, E>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+    hipLaunchKernelGGL((qb::k_i3_vjp_reg<T, P, E, false>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
   id = pl->begin(QB_K_ADJOINT, s);
   hipLaunchKernelGGL((qb::k_grad_pre<T>), dim3(blocks(nel * 8, 256)), dim3(256), 0, s, d, ncells, P * P);

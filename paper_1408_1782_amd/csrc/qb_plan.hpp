@@ -50,7 +50,9 @@ struct qb_plan_s {
   int P, E, NT, TPR;
   int wcells;  // cells per collision launch (the workspace holds this many)
   bool i3_pair = true;  // I_3 kernel pairs the Gauss-Legendre nodes (tuned; default per tile)
-  int vjp_variant = 0;  // I_3 adjoint: 0 accumulators in memory, 1 Y in registers, 2 Y and w_bar (tuned)
+  int vjp_variant = 0;  // I_3 adjoint: 0 row w_bar in memory, 1 in registers (tuned)
+  int vjp_E = 0;        // tile shape of the reverse-mode pipeline (tuned; 0: the forward tile)
+  int vjp_tab = 0;      // its table set
   int term_sel = 3;     // collision terms assembled: 1 C_c, 2 C_d, 3 both
   int limiter = 0;      // transport slope limiter: 0 minmod, 1 superbee, 2 MC, 3 van Leer
   int field_mode = 0;   // field term: 0 inside the Heun step, 1 exact rotation split around it
@@ -129,8 +131,10 @@ struct qb_plan_s {
 };
 
 
+// Device view of the plan with the table set `tab` (the forward pipeline
+// uses cur_tab, the reverse-mode pipeline vjp_tab).
 template <typename T>
-inline DevPlan<T> devplan(qb_plan_s* pl) {
+inline DevPlan<T> devplan(qb_plan_s* pl, int tab) {
   DevPlan<T> d;
   d.Nx = pl->prob.Nx;
   d.N = pl->prob.N;
@@ -140,7 +144,7 @@ inline DevPlan<T> devplan(qb_plan_s* pl) {
   d.L = (T)pl->prob.L;
   d.wc = (pl->term_sel & 1) ? (T)1 : (T)0;
   d.wd = (pl->term_sel & 2) ? (T)1 : (T)0;
-  const qb_plan_s::TabSet& ts = pl->tabs[pl->cur_tab];
+  const qb_plan_s::TabSet& ts = pl->tabs[tab];
   d.tw = (const T*)ts.tw;
   d.phip = (const T*)ts.phip;
   d.Kt = (const T*)ts.Kt;

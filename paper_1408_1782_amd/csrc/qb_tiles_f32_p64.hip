@@ -7,3 +7,6 @@ template bool collision_vjp_pipeline<float, 64, 32>(qb_plan_s*, const float*, co
 template bool collision_pipeline<float, 64, 16>(qb_plan_s*, const float*, float*, int, int, hipStream_t);
 template bool collision_vjp_pipeline<float, 64, 16>(qb_plan_s*, const float*, const float*, float*, int, int,
                                                    hipStream_t);
+template bool collision_pipeline<float, 64, 8>(qb_plan_s*, const float*, float*, int, int, hipStream_t);
+template bool collision_vjp_pipeline<float, 64, 8>(qb_plan_s*, const float*, const float*, float*, int, int,
+                                                  hipStream_t);

@@ -7,3 +7,6 @@ template bool collision_vjp_pipeline<double, 64, 32>(qb_plan_s*, const double*, 
 template bool collision_pipeline<double, 64, 16>(qb_plan_s*, const double*, double*, int, int, hipStream_t);
 template bool collision_vjp_pipeline<double, 64, 16>(qb_plan_s*, const double*, const double*, double*, int, int,
                                                    hipStream_t);
+template bool collision_pipeline<double, 64, 8>(qb_plan_s*, const double*, double*, int, int, hipStream_t);
+template bool collision_vjp_pipeline<double, 64, 8>(qb_plan_s*, const double*, const double*, double*, int, int,
+                                                  hipStream_t);

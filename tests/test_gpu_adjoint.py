@@ -79,17 +79,19 @@ def test_collision_vjp_matches_oracle(precision, N, J, M, ncells):
     plan.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("N,E,M", [(16, 8, 5), (32, 16, 4), (64, 32, 3), (64, 16, 4)])
+@pytest.mark.parametrize("N,E,M", [(16, 8, 5), (32, 16, 4), (32, 8, 5), (64, 32, 3), (64, 16, 4)])
 def test_collision_vjp_every_kernel_variant(precision, N, E, M, variant):
-    """Every I_3 adjoint kernel (accumulators in memory / registers) on
+    """Both I_3 adjoint kernels (row w cotangents in memory / registers) on
     every tile shape family, odd and even M, against the oracle."""
     import torch
     rng = np.random.default_rng(7 * N + M)
     w = wl.config(3, Nx=2, N=N)
     plan = make_plan(w, precision, 4, M)
-    plan.set_tile(E)
+    # the reverse-mode pipeline on its own tile (the forward keeps the default)
+    plan.set_adjoint_tile(E)
+    assert plan.config()["adjoint_tile"] == E
     plan.set_adjoint_variant(variant)
     lam = rng.standard_normal((2, N, N, 4))
     G = plan.collision_vjp(to_dev(w.W0, precision), to_dev(cot_api(lam), precision))
