@@ -285,7 +285,8 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
 
 /* Autotuner: time the collision pipeline on the plan's first `ncells` cells
  * for every compiled tile shape, with and without Gauss-Legendre node
- * pairing in the I_3 kernel, and keep the fastest; when the plan's
+ * pairing in the I_3 kernel, and keep the fastest; then the two launch
+ * shapes (qb_plan_set_persistent) on that tile; when the plan's
  * adjoint is enabled, also time the reverse-mode pipeline for every tile
  * shape and both I_3 adjoint kernels (row w cotangents in memory or in
  * registers, see qb_plan_config) and keep the fastest.  Synchronous; overwrites the
@@ -307,13 +308,21 @@ qb_status qb_plan_set_adjoint_tile(qb_plan plan, int32_t E);
 /* Use I_3 adjoint kernel `variant` (0 or 1, see qb_plan_config). */
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant);
 
+/* Launch shape of the two heavy collision kernels (I_1 / I_2 / I_4 and
+ * I_3): 0 (the default) launches one workgroup per task, (cell, term) or
+ * (cell, j); 1 launches a persistent grid of as many workgroups as are
+ * resident at once on the device (a multiple of 8), each striding over the
+ * task list.  Both compute the same values bit for bit; qb_plan_tune picks
+ * the faster.  For a batch the task list spans every problem of a grid size. */
+qb_status qb_plan_set_persistent(qb_plan plan, int32_t persistent);
+
 /* Current tile shape E, I_3 adjoint kernel (0: the shifted-field cotangent
  * of the current rows in registers, 1: also their w cotangent), whether
  * the I_3 kernel of this tile pairs the Gauss-Legendre nodes m and M-1-m
- * (1) or runs every node on its own (0), and the reverse-mode tile shape;
- * any pointer may be NULL. */
+ * (1) or runs every node on its own (0), the reverse-mode tile shape and
+ * the launch shape (qb_plan_set_persistent); any pointer may be NULL. */
 qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes,
-                         int32_t* adjoint_tile);
+                         int32_t* adjoint_tile, int32_t* persistent);
 
 /* ---------------------------------------------------------------------------
  * Batches of independent problems (uneven Nx and N) advanced together:
@@ -337,6 +346,11 @@ qb_status qb_batch_create(const qb_problem* problems, int32_t nprob, void* works
                           qb_batch* out);
 qb_status qb_batch_destroy(qb_batch batch);
 size_t qb_batch_bytes(qb_batch batch);
+
+/* Launch shape of the collision kernels of every N group (as
+ * qb_plan_set_persistent: each group's kernels stride over the tasks of all
+ * its problems' cells from one resident-sized grid); drops a recorded graph. */
+qb_status qb_batch_set_persistent(qb_batch batch, int32_t persistent);
 
 /* Run the autotuner (qb_plan_tune) for every N group of the batch. */
 qb_status qb_batch_tune(qb_batch batch, void* stream);

@@ -54,6 +54,7 @@ EXPORTS = (
     "qb_plan_config",
     "qb_plan_set_adjoint_variant",
     "qb_plan_set_adjoint_tile",
+    "qb_plan_set_persistent",
     "qb_plan_set_pairing",
     "qb_plan_set_terms",
     "qb_plan_set_scheme",
@@ -61,6 +62,7 @@ EXPORTS = (
     "qb_batch_destroy",
     "qb_batch_bytes",
     "qb_batch_tune",
+    "qb_batch_set_persistent",
     "qb_batch_step",
     "qb_profile",
     "qb_profile_read",
@@ -168,7 +170,9 @@ def _declare(lib):
     lib.qb_plan_tune.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
     lib.qb_plan_tune.restype = i32
     lib.qb_plan_config.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                   ctypes.POINTER(i32)]
+                                   ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.qb_plan_set_persistent.argtypes = [vp, i32]
+    lib.qb_plan_set_persistent.restype = i32
     lib.qb_plan_set_adjoint_tile.argtypes = [vp, i32]
     lib.qb_plan_set_adjoint_tile.restype = i32
     lib.qb_plan_config.restype = i32
@@ -186,6 +190,8 @@ def _declare(lib):
     lib.qb_batch_destroy.restype = i32
     lib.qb_batch_bytes.argtypes = [vp]
     lib.qb_batch_bytes.restype = ctypes.c_size_t
+    lib.qb_batch_set_persistent.argtypes = [vp, i32]
+    lib.qb_batch_set_persistent.restype = i32
     lib.qb_batch_tune.argtypes = [vp, vp]
     lib.qb_batch_tune.restype = i32
     lib.qb_batch_step.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), dbl, i32, ctypes.POINTER(vp), i32, vp]
@@ -544,6 +550,11 @@ class Plan:
         (0 follows the forward tile)."""
         _check(self.lib.qb_plan_set_adjoint_tile(self.handle, int(E)), "qb_plan_set_adjoint_tile")
 
+    def set_persistent(self, persistent):
+        """qb_plan_set_persistent: persistent (grid-stride) launches of the
+        heavy collision kernels, or one workgroup per task."""
+        _check(self.lib.qb_plan_set_persistent(self.handle, 1 if persistent else 0), "qb_plan_set_persistent")
+
     def set_adjoint_variant(self, v):
         """qb_plan_set_adjoint_variant: I_3 adjoint kernel 0 or 1."""
         _check(self.lib.qb_plan_set_adjoint_variant(self.handle, int(v)), "qb_plan_set_adjoint_variant")
@@ -570,11 +581,11 @@ class Plan:
     def config(self):
         """qb_plan_config: tile E, I_3 adjoint variant, node pairing and the
         reverse-mode tile in use."""
-        e, v, pn, ae = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        e, v, pn, ae, ps = (ctypes.c_int32() for _ in range(5))
         _check(self.lib.qb_plan_config(self.handle, ctypes.byref(e), ctypes.byref(v), ctypes.byref(pn),
-                                       ctypes.byref(ae)), "qb_plan_config")
+                                       ctypes.byref(ae), ctypes.byref(ps)), "qb_plan_config")
         return {"tile": e.value, "adjoint_variant": v.value, "paired_nodes": bool(pn.value),
-                "adjoint_tile": ae.value}
+                "adjoint_tile": ae.value, "persistent": bool(ps.value)}
 
     def profile(self, enable=True):
         """qb_profile: bracket every launch of this plan with HIP events."""
@@ -647,6 +658,10 @@ class Batch:
 
     def tune(self):
         _check(self.lib.qb_batch_tune(self.handle, _stream()), "qb_batch_tune")
+
+    def set_persistent(self, persistent):
+        """qb_batch_set_persistent: persistent (grid-stride) collision launches."""
+        _check(self.lib.qb_batch_set_persistent(self.handle, 1 if persistent else 0), "qb_batch_set_persistent")
 
     def step(self, Ws, Bs=None, dt=1e-3, nsteps=1, moments=None, graph=False):
         """qb_batch_step: nsteps steps of every problem in place."""

@@ -351,11 +351,14 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
 // (mu 0 + i mu 1), (mu 2 + i mu 3), re/im planes, col spec.
 template <typename T, int P, int E, bool WREG>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d, int ncells) {
-  using K = Kern<T, P, E>;
+  using K = Kern<T, P, E, true>;
   constexpr unsigned S = sizeof(T);
   // elements between scheduling barriers in the element loops, which bound
   // the loads in flight
-  constexpr int SG = 4;
+#ifndef QB_VJP_SG
+#define QB_VJP_SG 4
+#endif
+  constexpr int SG = QB_VJP_SG;
   // registers: the transform operand, Y of the rows, w_bar of the rows
   // (WREG) and the rows' four shifted fields (RREG), E values each per
   // field and thread, beside about 48 for addresses and temporaries
@@ -363,7 +366,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
   constexpr bool RREG = 2 * F + 2 * F + (WREG ? 2 * F : 0) + 4 * F + 48 <= I3Regs<T, P, E>::BUDGET;
   constexpr int RE = RREG ? E : 1;
   __shared__ T smem[K::LDS];
-  Fft2<T, P, E> eng;
+  typename K::Eng eng;
   setup(eng, smem, d.tw);
   const int task = xcd_task(blockIdx.x, gridDim.x);
   const int cell = task / d.J;
@@ -484,39 +487,40 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
         else
           return ld(buf, plane, n * K::NT);
       };
+      // The element loops are fused across the two convolutions of a nu:
+      // consuming q also builds the input of R (b_bar_nu is loaded once),
+      // and consuming R builds the input of the next nu's q (w_a0, w_a1
+      // are loaded once per nu).
+      T zr[E], zi[E];
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const unsigned o = n * K::NT;
+        const T sv = ld(rb, 0, o);
+        zr[n] = ld(rw, a0, o) * sv;
+        zi[n] = ld(rw, a1, o) * sv;
+        if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
+      }
 #pragma unroll 1
       for (int nu = 0; nu < 4; ++nu) {
         const T enu = nu == 0 ? (T)1 : (T)-1;  // eta_nu
-        T zr[E], zi[E];
-        // q_a,nu = Psi(w_a s_nu)
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T sv = ld(rb, nu, o);
-          zr[n] = ld(rw, a0, o) * sv;
-          zi[n] = ld(rw, a1, o) * sv;
-          if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
-        }
+        // q_a,nu = Psi(w_a s_nu); then R_a,nu = Psi(eta_a b_bar_nu s_a + eta_nu t_a w_nu)
         conv(zr, zi);
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
-          const T bb = c * ld(rl, nu, o);
+          const T b = ld(rl, nu, o), bb = c * b;
+          const T ta0v = row(ta0, rt, a0, n), ta1v = row(ta1, rt, a1, n);
           ya0[n] += ea0 * bb * zr[n];
           ya1[n] -= bb * zi[n];
-          rmw(rg, nu, o, enu * c * (row(ta0, rt, a0, n) * zr[n] + row(ta1, rt, a1, n) * zi[n]));
-          if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
-        }
-        // R_a,nu = Psi(eta_a b_bar_nu s_a + eta_nu t_a w_nu)
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          const unsigned o = n * K::NT;
-          const T bb = ld(rl, nu, o), wv = enu * ld(rw, nu, o);
-          zr[n] = ea0 * bb * row(sa0, rb, a0, n) + wv * row(ta0, rt, a0, n);
-          zi[n] = wv * row(ta1, rt, a1, n) - bb * row(sa1, rb, a1, n);
+          rmw(rg, nu, o, enu * c * (ta0v * zr[n] + ta1v * zi[n]));
+          const T wv = enu * ld(rw, nu, o);
+          zr[n] = ea0 * b * row(sa0, rb, a0, n) + wv * ta0v;
+          zi[n] = wv * ta1v - b * row(sa1, rb, a1, n);
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
         conv(zr, zi);
+        // next q input: s of the next nu (re-read on the last pass, unused)
+        const int nx = nu < 3 ? nu + 1 : 3;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
@@ -528,7 +532,11 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
             rmw(rg, a0, o, sv * zr[n]);
             rmw(rg, a1, o, sv * zi[n]);
           }
-          rmw(rc, nu, o, c * (ld(rw, a0, o) * zr[n] + ld(rw, a1, o) * zi[n]));
+          const T w0 = ld(rw, a0, o), w1 = ld(rw, a1, o);
+          rmw(rc, nu, o, c * (w0 * zr[n] + w1 * zi[n]));
+          const T sn = ld(rb, nx, o);
+          zr[n] = w0 * sn;
+          zi[n] = w1 * sn;
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }

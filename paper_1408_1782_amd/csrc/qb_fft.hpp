@@ -2,8 +2,12 @@
 //
 // A P x P complex field is spread over NT = P * TPR threads of a workgroup,
 // TPR = P / E threads per line, E elements per thread.  Thread t owns line
-// l = t / TPR and lane-in-line q = t % TPR (the TPR lanes of a line are
-// adjacent lanes of one wavefront).
+// l = t / TPR and lane-in-line q (the TPR lanes of a line are adjacent lanes
+// of one wavefront).  For TPR <= 4, q = t % TPR.  For TPR = 8 the lanes of
+// the upper half are relabelled, q = p ^ 3 for p = t % 8 >= 4 (lanes
+// 4, 5, 6, 7 hold q = 7, 6, 5, 4), so that the distance-4 partner of every
+// lane, q ^ 4, is the lane 7 - p: one row_half_mirror move instead of a quad
+// permute and a mirror.  The partners at distance 2 and 1 stay p ^ 2, p ^ 1.
 //
 //   "strided"  layout: element index  x = q + TPR * n,        n = 0..E-1
 //   "blocked"  layout: element index  k + E * bitrev(q),      k = 0..E-1
@@ -17,7 +21,8 @@
 //
 // 2D: rows (index x, line = y) and columns (index y, line = kx).  The field
 // moves between row and column ownership through an LDS transpose, one real
-// component at a time, so the LDS buffer holds P * (P + 1) scalars.
+// component at a time (both at once in workgroups that fill a CU and have
+// the LDS for two planes), through a padded P x P buffer per component.
 //
 //   row real (strided in x) --fwd rows--> row spectra (blocked in kx)
 //     --T1--> column real (strided in y) --fwd cols--> column spectra
@@ -168,9 +173,9 @@ __device__ __forceinline__ void reg_fft(T (&zr)[E], T (&zi)[E]) {
 }
 
 // ------------------------------------------------------------------ lane shuffles
-// Value of lane (lane ^ MASK) for MASK in {1, 2, 4}, by DPP moves within a row
-// of 16 lanes: quad_perm for 1 and 2, quad_perm [3,2,1,0] then
-// row_half_mirror (lane i -> 7 - i in each group of 8) for 4.
+// Value of lane (lane ^ MASK) for MASK in {1, 2}, by a DPP quad_perm move,
+// and for MASK = 7 the value of lane 7 - i in each group of 8 lanes
+// (row_half_mirror): the distance-4 partner under the TPR = 8 lane labels.
 template <int MASK>
 __device__ __forceinline__ int xor_lane_i32(int v) {
   if constexpr (MASK == 1) {
@@ -178,9 +183,8 @@ __device__ __forceinline__ int xor_lane_i32(int v) {
   } else if constexpr (MASK == 2) {
     return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
   } else {
-    static_assert(MASK == 4, "lane mask must be 1, 2 or 4");
-    const int t = __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
-    return __builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false);        // row_half_mirror
+    static_assert(MASK == 7, "lane mask must be 1, 2 or 7");
+    return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false);  // row_half_mirror
   }
 }
 
@@ -198,7 +202,7 @@ __device__ __forceinline__ double xor_lane(double v) {
 }
 
 // ------------------------------------------------------------------ engine
-template <typename T, int P_, int E_>
+template <typename T, int P_, int E_, bool XB_ = false>
 struct Fft2 {
   static constexpr int P = P_;
   static constexpr int E = E_;
@@ -220,7 +224,13 @@ struct Fft2 {
 #endif
   static constexpr int ROUNDS = (P * LD * (int)sizeof(T) > QB_XPOSE_SPLIT_BYTES && P / 2 >= E) ? 2 : 1;
   static constexpr int RP = P / ROUNDS;
-  static constexpr int LDS_SCALARS = RP * LD;
+  static constexpr int PLANE = RP * LD;  // one real plane of the transpose buffer
+  // Kernels whose workgroups of 512 threads or more fill a compute unit on
+  // their own (one per CU at their register use) may ask (XB_) to move the
+  // real and imaginary planes together through two buffers: two barriers
+  // per transpose instead of four, where every barrier idles the whole CU.
+  static constexpr bool XB = XB_ && ROUNDS == 1 && NT >= 512 && 2 * PLANE * (int)sizeof(T) <= 96 * 1024;
+  static constexpr int LDS_SCALARS = (XB ? 2 : 1) * PLANE;
   static_assert(TPR >= 1 && TPR <= 8 && (TPR & (TPR - 1)) == 0, "TPR must be 1, 2, 4 or 8");
   static_assert(E * TPR == P, "E * TPR must equal P");
   static_assert(P % BW == 0, "P must be a multiple of the bank width");
@@ -232,10 +242,13 @@ struct Fft2 {
   static constexpr int TWS = 2 * E + 2;
   static constexpr int TW_SCALARS = TPR * TWS;
 
+  // logical lane q of physical lane p (an involution, see the header)
+  static __host__ __device__ constexpr int lane_label(int p) { return TPR == 8 ? p ^ (3 * (p >> 2)) : p; }
+
   __device__ __forceinline__ void init(T* lds_buf, const T* twi) {
     t = threadIdx.x;
     line = t / TPR;
-    q = t % TPR;
+    q = lane_label(t % TPR);
     bq = bitrev_rt(q, LB);
     lds = lds_buf;
     tw = twi;
@@ -288,7 +301,7 @@ struct Fft2 {
       w8<-1>((q & 4) ? (q & 3) : 0, wr, wi);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
-        const T orr = xor_lane<4>(zr[k]), oi = xor_lane<4>(zi[k]);
+        const T orr = xor_lane<7>(zr[k]), oi = xor_lane<7>(zi[k]);
         const T dr = sg * zr[k] + orr, di = sg * zi[k] + oi;
         zr[k] = dr * wr - di * wi;
         zi[k] = dr * wi + di * wr;
@@ -346,7 +359,7 @@ struct Fft2 {
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const T ar = zr[k] * wr - zi[k] * wi, ai = zr[k] * wi + zi[k] * wr;
-        const T orr = xor_lane<4>(ar), oi = xor_lane<4>(ai);
+        const T orr = xor_lane<7>(ar), oi = xor_lane<7>(ai);
         zr[k] = sg * ar + orr;
         zi[k] = sg * ai + oi;
       }
@@ -373,13 +386,47 @@ struct Fft2 {
 
   // T1: row spectra (blocked in kx, line = y) -> column real (strided in y, line = kx)
   __device__ __forceinline__ void t_rows_to_cols(T (&zr)[E], T (&zi)[E]) const {
-    xpose_rb_to_cs(zr);
-    xpose_rb_to_cs(zi);
+    if constexpr (XB) {
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int a = addr(bk(k), line) + off_of(bk(k));
+        lds[a] = zr[k];
+        lds[PLANE + a] = zi[k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const int a = addr(line, sx(n)) + off_of(line);
+        zr[n] = lds[a];
+        zi[n] = lds[PLANE + a];
+      }
+      __syncthreads();
+    } else {
+      xpose_rb_to_cs(zr);
+      xpose_rb_to_cs(zi);
+    }
   }
   // T2: column real (strided in y, line = kx) -> row spectra (blocked in kx, line = y)
   __device__ __forceinline__ void t_cols_to_rows(T (&zr)[E], T (&zi)[E]) const {
-    xpose_cs_to_rb(zr);
-    xpose_cs_to_rb(zi);
+    if constexpr (XB) {
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const int a = addr(line, sx(n)) + off_of(line);
+        lds[a] = zr[n];
+        lds[PLANE + a] = zi[n];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const int a = addr(bk(k), line) + off_of(bk(k));
+        zr[k] = lds[a];
+        zi[k] = lds[PLANE + a];
+      }
+      __syncthreads();
+    } else {
+      xpose_cs_to_rb(zr);
+      xpose_cs_to_rb(zi);
+    }
   }
 
   // With ROUNDS > 1 a thread may receive its column elements in an earlier

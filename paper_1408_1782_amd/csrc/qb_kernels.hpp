@@ -191,9 +191,9 @@ __global__ void k_state_to_api(const T* __restrict__ w, TA* __restrict__ W, int 
 }
 
 // ------------------------------------------------------------------ engine setup
-template <typename T, int P, int E>
+template <typename T, int P, int E, bool XB = false>
 struct Kern {
-  using Eng = Fft2<T, P, E>;
+  using Eng = Fft2<T, P, E, XB>;
   static constexpr int NT = Eng::NT;
   static constexpr int TPR = Eng::TPR;
   static constexpr int FSZ = P * P;
@@ -206,9 +206,9 @@ struct Kern {
   static constexpr int WAVES = (sizeof(T) == 4 && P == 128) ? QB_F32_P128_WAVES : 1;
 };
 
-template <typename T, int P, int E>
-__device__ __forceinline__ void setup(Fft2<T, P, E>& eng, T* smem, const T* tw) {
-  using F = Fft2<T, P, E>;
+template <typename T, int P, int E, bool XB>
+__device__ __forceinline__ void setup(Fft2<T, P, E, XB>& eng, T* smem, const T* tw) {
+  using F = Fft2<T, P, E, XB>;
   T* t2 = smem + F::LDS_SCALARS;
   // tw holds [q][k] rows of 2E scalars; LDS rows are TWS apart
   for (int i = threadIdx.x; i < 2 * P; i += blockDim.x) t2[(i / (2 * E)) * F::TWS + i % (2 * E)] = tw[i];
@@ -285,14 +285,17 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_dft_in(DevPlan<T> d, co
 // task 7   : I_2 accumulator S = sum_j (pi/J) sum_mu eta_mu
 //            IFFT(psi_j w_hat_mu) IFFT(psi'_j w_hat_mu)   (real space)
 template <typename T, int P, int E>
-__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
+__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int ncells) {
   using K = Kern<T, P, E>;
   constexpr unsigned S = sizeof(T);
   __shared__ T smem[K::LDS];
   Fft2<T, P, E> eng;
   setup(eng, smem, d.tw);
-  const int cell = blockIdx.x / 8;
-  const int task = blockIdx.x % 8;
+  // one (cell, task) per workgroup, or grid-stride when persistent
+#pragma unroll 1
+  for (int pt = blockIdx.x; pt < ncells * 8; pt += gridDim.x) {
+  const int cell = pt / 8;
+  const int task = pt % 8;
   const unsigned vo = threadIdx.x * S;
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
@@ -378,6 +381,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d) {
 #pragma unroll
     for (int n = 0; n < E; ++n) bst<T>(ro, Sacc[n], vo, (n * K::NT) * S);
   }
+  }  // tasks
 }
 
 // ------------------------------------------------------------------ I_3
@@ -446,7 +450,7 @@ __device__ __forceinline__ T pick4(int i, T a, T b, T c, T d) {
 
 template <typename T, int P, int E, bool PAIR>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_per_eu(Kern<T, P, E>::WAVES))) void k_i3(DevPlan<T> d, int ncells) {
-  using K = Kern<T, P, E>;
+  using K = Kern<T, P, E, true>;
   constexpr unsigned S = sizeof(T);
   constexpr bool SREG = I3Regs<T, P, E>::template sreg<PAIR>();
   // the current row pair's two shifted fields in registers for the nu loop
@@ -467,9 +471,15 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   // the loads in flight (measured: 4 at P = 128, 8 at P = 64)
   constexpr int SG = P >= 128 ? 4 : 8;
   const unsigned tid = threadIdx.x;
-  Fft2<T, P, E> eng;
+  typename K::Eng eng;
   setup(eng, smem, d.tw);
-  const int task = xcd_task(blockIdx.x, gridDim.x);
+  // one (cell, j) task per workgroup, or grid-stride over the tasks when
+  // the launch is persistent (a grid that is a multiple of 8 keeps every
+  // cell's tasks on the XCD that runs them)
+  const int ntask = ncells * d.J;
+#pragma unroll 1
+  for (int pt = blockIdx.x; pt < ntask; pt += gridDim.x) {
+  const int task = xcd_task(pt, ntask);
   const int cell = task / d.J;
   const int j = task % d.J;
   const unsigned vo = threadIdx.x * S;
@@ -654,6 +664,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
       for (int n = 0; n < E; ++n) bst<T>(ro, acc[f * K::FSZ + n * K::NT + tid], vo, (f * K::FSZ + n * K::NT) * S);
     }
   }
+  }  // tasks
 }
 
 // Real-space P-grid fields of C, elementwise: sums the per-j partials of I_3

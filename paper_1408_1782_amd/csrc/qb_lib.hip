@@ -29,6 +29,22 @@ bool hip_ok(hipError_t e, const char* what) {
 
 void set_error(const char* what) { g_last_error = what; }
 
+int persistent_grid(const void* kern, int threads) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find({kern, dev});
+  if (it != cache.end()) return it->second;
+  int per_cu = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess) per_cu = 1;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 8;
+  const int g = std::max(8, (std::max(per_cu, 1) * std::max(cus, 1)) / 8 * 8);
+  cache[{kern, dev}] = g;
+  return g;
+}
+
 namespace {
 
 // ------------------------------------------------------------------ quadrature (host, float64)
@@ -129,11 +145,14 @@ bool put(void* dst, const std::vector<double>& v) {
   return hip_ok(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
 }
 
-// col spec position of frequency indices (kx, ky) (FFT order)
+// col spec position of frequency indices (kx, ky) (FFT order): block ky / E
+// sits in the lane whose logical label is its bit reversal (the engine's
+// lane labels relabel the upper half of an 8-lane line, an involution)
 inline size_t colspec_index(int kx, int ky, int E, int TPR, int NT) {
   const int lb = qb::ilog2(TPR);
   const int q = qb::bitrev_rt(ky / E, lb);
-  const int t = kx * TPR + q;
+  const int lane = TPR == 8 ? q ^ (3 * (q >> 2)) : q;
+  const int t = kx * TPR + lane;
   return (size_t)(ky % E) * NT + t;
 }
 
@@ -908,6 +927,39 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
   if (!select_tile<T>(pl, best)) return QB_EHIP;
   pl->i3_pair = best_pair;
   if (chosen) *chosen = best;
+  {
+    // one workgroup per task against a persistent grid of resident
+    // workgroups striding over the tasks (same kernels, same results)
+    const TuneKey pkey{p.precision + 32, p.N, p.J, p.M, ncells};
+    auto pt = tune_cache().find(pkey);
+    if (pt != tune_cache().end()) {
+      pl->persistent = pt->second == 1;
+    } else {
+      T* w = (T*)pl->st0;
+      T* c = (T*)pl->cbuf;
+      if (!hip_ok(hipMemsetAsync(w, 0, (size_t)4 * p.Nx * p.N * p.N * sizeof(T), s), "hipMemsetAsync"))
+        return QB_EHIP;
+      const bool prof = pl->profiling;
+      pl->profiling = false;
+      hipEvent_t a = pl->event(), b = pl->event();
+      float t[2] = {0.f, 0.f};
+      for (int v = 0; v < 2; ++v) {
+        pl->persistent = v == 1;
+        if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;  // warm-up
+        (void)hipEventRecord(a, s);
+        for (int r = 0; r < 2; ++r)
+          if (!collision_any<T>(pl, w, c, ncells, s)) return QB_EHIP;
+        (void)hipEventRecord(b, s);
+        if (!hip_ok(hipEventSynchronize(b), "hipEventSynchronize")) return QB_EHIP;
+        (void)hipEventElapsedTime(&t[v], a, b);
+      }
+      pl->pool.push_back(a);
+      pl->pool.push_back(b);
+      pl->profiling = prof;
+      pl->persistent = t[1] < t[0];
+      tune_cache()[pkey] = pl->persistent ? 1 : 0;
+    }
+  }
   if (pl->adjoint) {
     // the reverse-mode pipeline: every tile shape (its own table set) and
     // both I_3 adjoint kernels; the choice is cached as 16 E + variant
@@ -1609,6 +1661,12 @@ qb_status qb_plan_set_adjoint_tile(qb_plan plan, int32_t E) {
   return ok ? QB_OK : QB_EHIP;
 }
 
+qb_status qb_plan_set_persistent(qb_plan plan, int32_t persistent) {
+  if (!plan || persistent < 0 || persistent > 1) return QB_EINVAL;
+  plan->persistent = persistent == 1;
+  return QB_OK;
+}
+
 qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant) {
   if (!plan || variant < 0 || variant > 1) return QB_EINVAL;
   plan->vjp_variant = variant;
@@ -1616,8 +1674,9 @@ qb_status qb_plan_set_adjoint_variant(qb_plan plan, int32_t variant) {
 }
 
 qb_status qb_plan_config(qb_plan plan, int32_t* tile, int32_t* adjoint_variant, int32_t* paired_nodes,
-                         int32_t* adjoint_tile) {
+                         int32_t* adjoint_tile, int32_t* persistent) {
   if (!plan) return QB_EINVAL;
+  if (persistent) *persistent = plan->persistent ? 1 : 0;
   if (tile) *tile = plan->E;
   if (adjoint_tile) *adjoint_tile = plan->tabs[plan->vjp_tab].E;
   if (adjoint_variant) *adjoint_variant = plan->vjp_variant;
@@ -1678,6 +1737,13 @@ qb_status qb_batch_tune(qb_batch batch, void* stream) {
     if (st != QB_OK) return st;
   }
   batch->drop_graph();  // recorded launches refer to the previous tiles
+  return QB_OK;
+}
+
+qb_status qb_batch_set_persistent(qb_batch batch, int32_t persistent) {
+  if (!batch || persistent < 0 || persistent > 1) return QB_EINVAL;
+  for (auto& g : batch->groups) g.plan->persistent = persistent == 1;
+  batch->drop_graph();  // recorded launches use the previous shape
   return QB_OK;
 }
 

@@ -12,14 +12,22 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, 
   int id = pl->begin(QB_K_DFT_IN, s);
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
+  // persistent launches: at most the workgroups that are resident at once
+  // (rounded down to a multiple of 8), grid-striding over the task list
+  auto grid = [&](int ntask, const void* kern) {
+    return pl->persistent ? std::min(ntask, persistent_grid(kern, NT)) : ntask;
+  };
   id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(grid(ncells * 8, (const void*)qb::k_terms<T, P, E>)), dim3(NT),
+                     0, s, d, ncells);
   pl->end(id, s);
   id = pl->begin(QB_K_I3, s);
   if (pl->i3_pair)
-    hipLaunchKernelGGL((qb::k_i3<T, P, E, true>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+    hipLaunchKernelGGL((qb::k_i3<T, P, E, true>), dim3(grid(ncells * d.J, (const void*)qb::k_i3<T, P, E, true>)),
+                       dim3(NT), 0, s, d, ncells);
   else
-    hipLaunchKernelGGL((qb::k_i3<T, P, E, false>), dim3(ncells * d.J), dim3(NT), 0, s, d, ncells);
+    hipLaunchKernelGGL((qb::k_i3<T, P, E, false>), dim3(grid(ncells * d.J, (const void*)qb::k_i3<T, P, E, false>)),
+                       dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
   const size_t nel = (size_t)ncells * P * P;
   hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
@@ -39,7 +47,7 @@ bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
   id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
   id = pl->begin(QB_K_ADJOINT, s);
   hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, cell0);

@@ -18,6 +18,11 @@ bool hip_ok(hipError_t e, const char* what);
 // Records a message for qb_last_error().
 void set_error(const char* what);
 
+// Workgroups of `threads` threads of kernel `kern` resident on the current
+// device at once (occupancy x compute units), rounded down to a multiple of
+// 8 (one per XCD, so a grid stride keeps its XCD); at least 8.
+int persistent_grid(const void* kern, int threads);
+
 // Bump allocator over caller-owned device memory: the library never
 // allocates device memory itself.  In measuring mode it only adds up the
 // aligned sizes (the pointers stay null), which is how the workspace size
@@ -56,6 +61,7 @@ struct qb_plan_s {
   int term_sel = 3;     // collision terms assembled: 1 C_c, 2 C_d, 3 both
   int limiter = 0;      // transport slope limiter: 0 minmod, 1 superbee, 2 MC, 3 van Leer
   int field_mode = 0;   // field term: 0 inside the Heun step, 1 exact rotation split around it
+  bool persistent = false;  // collision kernels grid-stride over their tasks from a resident-sized grid
   // quadrature tables in the FFT engine's element order, one set per tile
   // shape E (elements per thread) that has been selected on this plan
   struct TabSet {

@@ -24,6 +24,18 @@ def test_i3_transform_and_flop_counts():
     assert math.isclose(bench.i3_flops(256, 64, 32, 64, True), 6.013e12, rel_tol=1e-3)
 
 
+def test_i3_algorithmic_count_and_io():
+    """The method's own count: 36 unpacked transforms per (j, m) (4 shifts,
+    16 convolutions of two transforms), 2.16e13 flop for the slab launch;
+    the kernel's minimum traffic: 21 P x P fields per cell."""
+    n = 128 * 128
+    assert math.isclose(bench.i3_flops_algorithmic(256, 64, 32, 64), 256 * 36 * 32 * 64 * 5.0 * n * math.log2(n))
+    assert math.isclose(bench.i3_flops_algorithmic(256, 64, 32, 64), 2.164e13, rel_tol=1e-3)
+    # pairing and packing save 36 * 2 / 20 = 3.6x against the method's count
+    assert math.isclose(bench.i3_flops_algorithmic(1, 64, 32, 64) / bench.i3_flops(1, 64, 32, 64, True), 3.6)
+    assert bench.i3_io_bytes(256, 64, 32, 4) == 256 * 21 * 128 * 128 * 4
+
+
 def _fake_components(N, seed):
     rng = np.random.default_rng(seed)
     return rng.standard_normal((4, N, N))

@@ -249,16 +249,16 @@ def test_evolve_gradient_finite_differences():
 
 def test_evolve_gradient_finite_differences_full_shape():
     """The gradient workload at its full shape (128 cells, N = 32,
-    J = M = 32, float64), 10 steps with checkpoints every 4: central
-    differences with h = 1e-6 on four field components and h = 1e-7 on two
-    Hermitian directions of the (perturbed, see above) initial state
-    against the adjoint gradient."""
+    J = M = 32, float64), 20 steps with checkpoints every 5 (three segments
+    recomputed): central differences with h = 1e-6 on 16 field components
+    and h = 1e-7 on 8 Hermitian directions of the (perturbed, see above)
+    initial state against the adjoint gradient."""
     import torch
     import paper_1408_1782_amd as qb
     rng = np.random.default_rng(56)
     w = wl.config(5)
     plan = make_plan(w, "f64", w.J, w.M)
-    steps = 10
+    steps = 20
     h2 = (2 * w.L / w.N) ** 2
     wt = torch.from_numpy(wl.adjoint_loss_weight(w.Nx)).cuda()
 
@@ -268,29 +268,36 @@ def test_evolve_gradient_finite_differences_full_shape():
     base = w.W0 + pauli.from_pauli(0.05 * rng.standard_normal((w.Nx, w.N, w.N, 4)))
     W0 = to_dev(base, "f64").requires_grad_(True)
     B = torch.from_numpy(w.B).cuda().contiguous().requires_grad_(True)
-    loss_of(qb.evolve(plan, W0, B, w.dt, steps, checkpoint_every=4)).backward()
+    loss_of(qb.evolve(plan, W0, B, w.dt, steps, checkpoint_every=5)).backward()
 
     def run(Wi, Bi):
         W = Wi.detach().clone().contiguous()
         plan.step(W, Bi.detach().contiguous(), w.dt, steps)
         return loss_of(W).item()
 
-    # field components where the observable's weight is not negligible
+    # field components where the observable's weight is not negligible; a
+    # difference quotient carries a rounding error of about eps |loss| / h
+    # (a few 1e-12 here), so components far below the largest are held to
+    # an absolute bar of 1e-6 of the largest field gradient
     g = wl.adjoint_loss_weight(w.Nx)
     cells = np.argsort(g)[-32:]
-    for _ in range(4):
-        c, k = int(rng.choice(cells)), int(rng.integers(3))
+    gmax = B.grad.abs().max().item()
+    picks = rng.choice(len(cells) * 3, 16, replace=False)
+    for pk in picks:
+        c, k = int(cells[pk // 3]), int(pk % 3)
         dB = torch.zeros_like(B)
         dB[c, k] = 1.0
         h = 1e-6
         fd = (run(W0, B + h * dB) - run(W0, B - h * dB)) / (2 * h)
         ad = B.grad[c, k].item()
-        assert abs(fd - ad) <= 1e-5 * abs(ad) + 1e-12, (c, k, fd, ad)
-    for _ in range(2):
+        print(f"field component ({c}, {k}): fd {fd:.10e} adjoint {ad:.10e} (largest {gmax:.3e})", flush=True)
+        assert abs(fd - ad) <= 1e-5 * abs(ad) + 1e-6 * gmax, (c, k, fd, ad, gmax)
+    for i in range(8):
         d = pauli.from_pauli(0.05 * rng.standard_normal((w.Nx, w.N, w.N, 4)))
         dW = to_dev(d, "f64")
         h = 1e-7
         fd = (run(W0 + h * dW, B) - run(W0 - h * dW, B)) / (2 * h)
         ad = torch.sum((torch.conj(W0.grad) * dW).real).item()
+        print(f"state direction {i}: fd {fd:.10e} adjoint {ad:.10e}", flush=True)
         assert abs(fd - ad) <= 1e-5 * abs(ad) + 1e-12, (fd, ad)
     plan.close()

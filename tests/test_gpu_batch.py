@@ -85,22 +85,27 @@ def _batch_members(precision):
     return [(a, a.B), (b, b.B), (c, None), (d, d.B)]
 
 
+@pytest.mark.parametrize("persistent,graph", [(False, False), (True, False), (True, True)])
 @pytest.mark.parametrize("precision", ["f32", "f64"])
-def test_batch_equals_single_problem_runs(precision):
-    """Each problem of a batch ends bitwise where its own plan takes it,
-    with the same moments."""
+def test_batch_equals_single_problem_runs(precision, persistent, graph):
+    """Each problem of a batch ends bitwise where its own plan (one
+    workgroup per task) takes it, with the same moments: with one workgroup
+    per task, with the persistent launches that stride over every problem's
+    tasks, and with the persistent launches recorded in a graph."""
     import torch
     import paper_1408_1782_amd as qb
     J, M = 4, 4
     mem = _batch_members(precision)
     dt, steps = 2.5e-4, 2
     batch = qb.Batch([problem(w, precision, J, M) for w, _ in mem])
+    batch.set_persistent(persistent)
     Ws = [to_dev(w.W0, precision) for w, _ in mem]
     Bs = [None if B is None else torch.from_numpy(B).cuda().contiguous() for _, B in mem]
     moms = [torch.zeros((steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda") for w, _ in mem]
-    batch.step(Ws, Bs, dt, steps, moms)
+    batch.step(Ws, Bs, dt, steps, moms, graph=graph)
     for k, (w, _) in enumerate(mem):
         plan = qb.Plan(problem(w, precision, J, M))
+        plan.set_persistent(False)
         W = to_dev(w.W0, precision)
         m = torch.zeros((steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda")
         plan.step(W, Bs[k], dt, steps, m)
