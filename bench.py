@@ -266,14 +266,15 @@ def run_adjoint(steps, every):
             "grad_norms": {"W0": float(gW.abs().max()), "B": float(gB.abs().max())}}
 
 
-def run_batch(steps, nprob):
+def run_batch(steps, nprob, replays=1):
     """Batched throughput on the uneven-batch workload (64 periodic problems,
     Nx ~ U{32, 64, 128, 256, 512}, N ~ U{32, 64}, J = 32, M = N, B = 0,
     dt = 2.5e-4, float32 with float64 moments): tile and launch-shape
     autotuning, then one call of `steps` steps recorded as a HIP graph
     (capture, instantiation and its first launch, reported as capture_s),
-    then the recorded graph replayed once and timed alone (the `value`).
-    The N = 64 problems alone are timed the same way as a second batch."""
+    then that graph replayed `replays` times, each replay timed alone (the
+    `value` is cells * steps * replays over the replay time).  The N = 64
+    problems alone are timed the same way as a second batch."""
     import torch
     import paper_1408_1782_amd as qb
     import workloads
@@ -286,26 +287,29 @@ def run_batch(steps, nprob):
         batch.tune()
         Ws = [torch.from_numpy(w.W0).to(torch.complex64).cuda().contiguous() for w in sel]
         moms = [torch.zeros((steps + 1, w.Nx, 7), dtype=torch.float64, device="cuda") for w in sel]
+        cells = sum(w.Nx for w in sel)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         batch.step(Ws, None, wls[0].dt, steps, moms, graph=True)   # capture + first launch
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        batch.step(Ws, None, wls[0].dt, steps, moms, graph=True)   # replay of the recorded graph
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        cells = sum(w.Nx for w in sel)
-        log(f"[batch {label}] {len(sel)} problems, {cells} cells, {steps} step(s): capture + first run "
-            f"{t1 - t0:.3f} s, replay {t2 - t1:.3f} s")
+        capture = time.perf_counter() - t0
+        log(f"[batch {label}] {len(sel)} problems, {cells} cells, {steps}-step graph: capture + first run {capture:.3f} s")
+        times = []
+        for r in range(replays):
+            t1 = time.perf_counter()
+            batch.step(Ws, None, wls[0].dt, steps, moms, graph=True)   # replay of the recorded graph
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            log(f"[batch {label}] replay {r + 1}/{replays}: {times[-1]:.3f} s")
         finite = all(bool(torch.isfinite(torch.view_as_real(W)).all()) for W in Ws)
         batch.close()
-        return {"problems": len(sel), "cells": cells, "capture_s": t1 - t0, "replay_s": t2 - t1,
-                "value": cells * steps / (t2 - t1), "finite": finite}
+        return {"problems": len(sel), "cells": cells, "capture_s": capture, "replays": replays,
+                "replay_s": times, "value": cells * steps * replays / sum(times), "finite": finite}
 
     full = one(wls, "all")
     sub = one([w for w in wls if w.N == 64], "N=64")
-    return {"workload": "uneven_batch", "unit": "cells*steps/s", "dtype": "f32", "steps": steps,
-            "graph": "captured once, replayed", "all": full, "N64": sub,
+    return {"workload": "uneven_batch", "unit": "cells*steps/s", "dtype": "f32", "steps_per_graph": steps,
+            "replayed_steps": steps * replays, "graph": "captured once, replayed", "all": full, "N64": sub,
             "N32_cells": sum(w.Nx for w in wls if w.N == 32)}
 
 
@@ -613,6 +617,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="steps of the uneven-batch measurement (0 skips it)")
     ap.add_argument("--batch-problems", type=int, default=64, help="problems in the uneven batch")
+    ap.add_argument("--batch-replays", type=int, default=1, help="timed replays of the recorded batch graph")
+    ap.add_argument("--batch-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (scale for HBM byte counters)")
     ap.add_argument("--convergence", action="store_true",
@@ -636,6 +642,9 @@ def main():
         return
     if args.slab_record > 0:
         print(json.dumps(run_slab_record(args.slab_record)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(run_batch(args.batch_steps, args.batch_problems, args.batch_replays)), flush=True)
         return
 
     import workloads
@@ -729,7 +738,7 @@ def main():
         out["adjoint_forward_ratio"] = adj["ratio"]
         out["adjoint"] = adj
     if args.batch_steps > 0:
-        out["batched"] = run_batch(args.batch_steps, args.batch_problems)
+        out["batched"] = run_batch(args.batch_steps, args.batch_problems, args.batch_replays)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

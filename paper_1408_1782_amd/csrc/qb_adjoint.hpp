@@ -121,34 +121,41 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_lam_in(DevPlan<T> d, co
 //   acot[7]     cotangent of the I_2 accumulator S
 //   acot[8..11] cotangent of the I_3 sums b_nu
 //   acot[12..15] the explicit dependence of r on w_mu
+// Part 0 writes acot[0..11], which need only lam and w; part 1 writes
+// acot[12..15] from the forward fields g, y (terms[0..6]) and S (the sum
+// of its per-component parts spart[0..3]), which k_terms_vjp produces.
 template <typename T>
-__global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz) {
+__global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz, int part) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)ncells * fsz) return;
   const size_t cell = idx / fsz, e = idx % fsz;
   const T* lp = d.lamP + cell * 4 * fsz + e;
   const T* wp = d.wP + cell * 5 * fsz + e;
-  const T* tr = d.terms + cell * 8 * fsz + e;
   const T l0 = lp[0], l1 = lp[fsz], l2 = lp[2 * fsz], l3 = lp[3 * fsz];
   const T w0 = wp[0], w1 = wp[fsz], w2 = wp[2 * fsz], w3 = wp[3 * fsz];
-  const T g1 = tr[0], g2 = tr[fsz], g3 = tr[2 * fsz];
-  const T y0 = tr[3 * fsz], y1 = tr[4 * fsz], y2 = tr[5 * fsz], y3 = tr[6 * fsz];
-  const T Sv = tr[7 * fsz];
   const T pi = (T)kPi, two = (T)2, tp = (T)(2.0 * kPi);
   T* o = d.acot + cell * 16 * fsz + e;
-  // r_k = -2 (g x w)_k + ...  (C_c);  r_0, r_k of A, B, Cq (see k_assemble)
-  o[0] = two * (w3 * l2 - w2 * l3);
-  o[fsz] = two * (w1 * l3 - w3 * l1);
-  o[2 * fsz] = two * (w2 * l1 - w1 * l2);
-  o[3 * fsz] = tp * (w0 * l0 + w1 * l1 + w2 * l2 + w3 * l3);
-  o[4 * fsz] = tp * (-w1 * l0 - w0 * l1);
-  o[5 * fsz] = tp * (-w2 * l0 - w0 * l2);
-  o[6 * fsz] = tp * (-w3 * l0 - w0 * l3);
-  o[7 * fsz] = pi * (two * ((T)1 - w0) * l0 - two * (w1 * l1 + w2 * l2 + w3 * l3));
-  o[8 * fsz] = -tp * l0;
-  o[9 * fsz] = tp * l1;
-  o[10 * fsz] = tp * l2;
-  o[11 * fsz] = tp * l3;
+  if (part == 0) {
+    // r_k = -2 (g x w)_k + ...  (C_c);  r_0, r_k of A, B, Cq (see k_assemble)
+    o[0] = two * (w3 * l2 - w2 * l3);
+    o[fsz] = two * (w1 * l3 - w3 * l1);
+    o[2 * fsz] = two * (w2 * l1 - w1 * l2);
+    o[3 * fsz] = tp * (w0 * l0 + w1 * l1 + w2 * l2 + w3 * l3);
+    o[4 * fsz] = tp * (-w1 * l0 - w0 * l1);
+    o[5 * fsz] = tp * (-w2 * l0 - w0 * l2);
+    o[6 * fsz] = tp * (-w3 * l0 - w0 * l3);
+    o[7 * fsz] = pi * (two * ((T)1 - w0) * l0 - two * (w1 * l1 + w2 * l2 + w3 * l3));
+    o[8 * fsz] = -tp * l0;
+    o[9 * fsz] = tp * l1;
+    o[10 * fsz] = tp * l2;
+    o[11 * fsz] = tp * l3;
+    return;
+  }
+  const T* tr = d.terms + cell * 8 * fsz + e;
+  const T* sp = d.spart + cell * 4 * fsz + e;
+  const T g1 = tr[0], g2 = tr[fsz], g3 = tr[2 * fsz];
+  const T y0 = tr[3 * fsz], y1 = tr[4 * fsz], y2 = tr[5 * fsz], y3 = tr[6 * fsz];
+  const T Sv = sp[0] + sp[fsz] + sp[2 * fsz] + sp[3 * fsz];
   const T q = pi * (-two * Sv + two * y0);
   o[12 * fsz] = q * l0 - tp * (y1 * l1 + y2 * l2 + y3 * l3);
   o[13 * fsz] = -tp * y1 * l0 + q * l1 - two * g3 * l2 + two * g2 * l3;
@@ -157,15 +164,23 @@ __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz) {
 }
 
 // ------------------------------------------------------------------ I_1, I_4, I_2
-// Transpose of k_terms, one workgroup per (cell, task).
+// Transpose of k_terms, one workgroup per (cell, task), fused with the
+// forward fields the transpose of the assembly needs (k_terms computes
+// the same fields; running both here shares their inner transforms).
 // Tasks 0..6 (I_1 with l = task + 1, I_4 with g = task - 3):
 //   forward  a_j = inv2(in_j w_hat_g), c_j = fwd2(f0 a_j), field = Re inv2(sum_j out_j c_j)
 //   reverse  d = conj(F) field_bar;  b_j = F(out_j d);
 //            f0_bar += Re(a_j b_j);  w_hat_g_bar += in_j conj(F)(f0 b_j)
+//   (four transforms per j: b_j, a_j, c_j and the last one; field goes to
+//   terms[task])
 // Tasks 7..10 (I_2, one Pauli component mu = task - 7 each, so that every
 // task does three transforms per j):
 //            S = sum_j sum_mu e_mu A_j,mu B_j,mu with A + iB = inv2(w_hat_mu (psi_j + i psi'_j)):
 //            w_hat_mu_bar += psi_j conj(F)(S_bar e_mu B) + psi'_j conj(F)(S_bar e_mu A)
+//   (the component's share sum_j e_mu A B of S goes to spart[mu])
+// The field cotangents (acot[0..7]) depend only on lam and w, so they are
+// ready before this kernel; the dependence of the assembly on the fields
+// themselves (acot[12..15]) is formed after it.
 constexpr int kTermsVjpTasks = 11;
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d) {
@@ -187,8 +202,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
     const rsrc_t rin = mkbuf(task < 3 ? d.phip : d.psip, tabn);
     const rsrc_t rout = mkbuf(task < 3 ? d.Kt : d.psiw, tabn);
     const rsrc_t rd = mkbuf(d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
+    const rsrc_t rc = mkbuf(d.fwa + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
     const rsrc_t rf = mkbuf(d.gf0 + ((size_t)cell * 7 + task) * K::FSZ, K::FSZ);
     const rsrc_t rg = mkbuf(d.gspec + ((size_t)cell * 11 + task) * 2 * K::FSZ, 2 * K::FSZ);
+    const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * 8 + task) * K::FSZ, K::FSZ);
     const unsigned fg = 2 * g * K::FSZ;
     {
       // d = conj(F) field_bar = conj(fwd2(field_bar)) for the real field_bar
@@ -241,9 +258,31 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         T fb = zr[n] * br - zi[n] * bi;
         if (j != 0) fb += bld<T>(rf, vo, o * S);
         bst<T>(rf, fb, vo, o * S);
-        // conj(f0 b_j), transformed by fwd2 below
-        zr[n] = f0 * br;
-        zi[n] = -f0 * bi;
+        // forward: f0 a_j, transformed by fwd2 below
+        zr[n] *= f0;
+        zi[n] *= f0;
+      }
+      // c_j = fwd2(f0 a_j); the forward accumulator gets out_j c_j
+      eng.fwd2(zr, zi);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const unsigned o = k * K::NT;
+        const T a = bld<T>(rout, vo, (tj + o) * S);
+        T ar = a * zr[k], ai = a * zi[k];
+        // read at j = 0 too (not yet written) and dropped by a select
+        const T pr = bld<T>(rc, vo, o * S), pi = bld<T>(rc, vo, (K::FSZ + o) * S);
+        ar += j != 0 ? pr : (T)0;
+        ai += j != 0 ? pi : (T)0;
+        bst<T>(rc, ar, vo, o * S);
+        bst<T>(rc, ai, vo, (K::FSZ + o) * S);
+      }
+      // conj(f0 b_j), transformed by fwd2 below
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        const unsigned o = n * K::NT;
+        const T f0 = bld<T>(rw, vo, (4 * K::FSZ + o) * S);
+        zr[n] = f0 * bld<T>(rt, vo, o * S);
+        zi[n] = -f0 * bld<T>(rt, vo, (K::FSZ + o) * S);
       }
       eng.fwd2(zr, zi);
 #pragma unroll
@@ -259,11 +298,26 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         bst<T>(rg, xi, vo, (K::FSZ + o) * S);
       }
     }
+    // the forward field: Re inv2(sum_j out_j c_j)
+    T zr[E], zi[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+      const unsigned o = k * K::NT;
+      zr[k] = bld<T>(rc, vo, o * S);
+      zi[k] = bld<T>(rc, vo, (K::FSZ + o) * S);
+    }
+    eng.inv2(zr, zi);
+#pragma unroll
+    for (int n = 0; n < E; ++n) bst<T>(ro, zr[n], vo, (n * K::NT) * S);
   } else {
     const T wj = (T)(kPi / d.J);
     const rsrc_t rps = mkbuf(d.psi, tabn);
     const rsrc_t rpp = mkbuf(d.psip, tabn);
     const int mu = task - 7;
+    const rsrc_t rsp = mkbuf(d.spart + ((size_t)cell * 4 + mu) * K::FSZ, K::FSZ);
+    T Sacc[E];
+#pragma unroll
+    for (int n = 0; n < E; ++n) Sacc[n] = 0;
 #pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
       const unsigned tj = j * K::FSZ;
@@ -283,6 +337,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         const T e = mu == 0 ? wj : -wj;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
+          Sacc[n] += e * zr[n] * zi[n];  // the forward accumulator's share
           const T sb = e * bld<T>(ra, vo, (7 * K::FSZ + n * K::NT) * S);
           bst<T>(rt, sb * zr[n], vo, (n * K::NT) * S);  // B_bar = S_bar e A
           zr[n] = sb * zi[n];                          // A_bar = S_bar e B
@@ -314,6 +369,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         }
       }
     }
+#pragma unroll
+    for (int n = 0; n < E; ++n) bst<T>(rsp, Sacc[n], vo, (n * K::NT) * S);
   }
 }
 
@@ -452,11 +509,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
         }
       }
     }
-    // Y (the S-transposed cotangent of this node pair) starts at zero
-#pragma unroll 1
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int n = 0; n < E; ++n) bst<T>(rc, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+    // Y (the S-transposed cotangent of this node pair) is first written by
+    // the first row pair's convolutions (every column nu), then accumulated
     const T c = d.wm[m];
 #pragma unroll 1
     for (int mp = 0; mp < 2; ++mp) {
@@ -533,7 +587,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
             rmw(rg, a1, o, sv * zi[n]);
           }
           const T w0 = ld(rw, a0, o), w1 = ld(rw, a1, o);
-          rmw(rc, nu, o, c * (w0 * zr[n] + w1 * zi[n]));
+          // first row pair: the old value is read (in bounds) but dropped by
+          // a select, which keeps the loop free of branches
+          // first row pair: the old value is read (in bounds) but dropped by
+          // a select, which keeps the loop free of branches
+          const unsigned yo = (nu * K::FSZ + o) * S;
+          const T yp = bld<T>(rc, vo, yo);
+          bst<T>(rc, c * (w0 * zr[n] + w1 * zi[n]) + (mp != 0 ? yp : (T)0), vo, yo);
           const T sn = ld(rb, nx, o);
           zr[n] = w0 * sn;
           zi[n] = w1 * sn;
@@ -551,7 +611,12 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
         }
       }
     }
-    // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3)
+    // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3).  Only its
+    // entries on Xi are read back (the input stage keeps Xi), so the other
+    // lanes' accesses get an offset past the buffer (loads 0, stores
+    // dropped; the planes were cleared in full at the start).
+    const int bx = centered<P>(kx);
+    const bool kx_in = bx > -P / 4 && bx < P / 4;
 #pragma unroll 1
     for (int pr = 0; pr < 2; ++pr) {
       T zr[E], zi[E];
@@ -565,12 +630,15 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
+        const int by = centered<P>(eng.bk(k));
+        const unsigned vk = (kx_in && by > -P / 4 && by < P / 4) ? vo : 0x80000000u;
         T er, ei;
         cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
         T xr, xi;
         cmul(zr[k], -zi[k], er, ei, xr, xi);
-        rmw(rg, 4 + 2 * pr, o, xr);
-        rmw(rg, 5 + 2 * pr, o, xi);
+        const unsigned fr = ((4 + 2 * pr) * K::FSZ + o) * S, fi = ((5 + 2 * pr) * K::FSZ + o) * S;
+        bst<T>(rg, bld<T>(rg, vk, fr) + xr, vk, fr);
+        bst<T>(rg, bld<T>(rg, vk, fi) + xi, vk, fi);
       }
     }
   }

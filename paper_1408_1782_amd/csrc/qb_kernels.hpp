@@ -70,6 +70,8 @@ struct DevPlan {
   T* i3t;    // [cells][J][4][P*P]  shifted cotangents of the I_3 sums for the current (j, m)
   T* lamh;   // [cells][4][P*P]     spectrum of lamP, packed pairs, col spec
   T* gsum;   // [cells][8][P*P]     gathered cotangents (k_grad_pre)
+  T* fwa;    // [cells][7][2][P*P]  spectral accumulators of the forward I_1 / I_4 fields in k_terms_vjp
+  T* spart;  // [cells][4][P*P]     I_2 accumulator S split by Pauli component (k_terms_vjp)
 };
 
 // ------------------------------------------------------------------ helpers
@@ -619,8 +621,18 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       }
-      // spectrum of the partner sums: conj(phase) fwd2(pa + i pb), accumulated
+      // spectrum of the partner sums: conj(phase) fwd2(pa + i pb), accumulated.
+      // Only its entries on Xi reach the output (k_combine keeps Xi), so
+      // the other lanes' buffer accesses get an offset past the buffer:
+      // their loads return 0 and their stores are dropped, without memory
+      // traffic and without a branch.
       const unsigned fr = (2 * mp) * K::FSZ, fi = (2 * mp + 1) * K::FSZ;
+      const int bx = centered<P>(kx);
+      const bool kx_in = bx > -P / 4 && bx < P / 4;
+      auto xi_off = [&](int k) {
+        const int by = centered<P>(eng.bk(k));
+        return (kx_in && by > -P / 4 && by < P / 4) ? vo : 0x80000000u;
+      };
       if (paired) {
         T zr[E], zi[E];
 #pragma unroll
@@ -628,30 +640,30 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
           zr[n] = pa[PAIR ? n : 0];
           zi[n] = pb[PAIR ? n : 0];
         }
-        if constexpr (PF) fetch_lds<T, K::NT, E>(rp, pf, vo, fr * S);
         eng.fwd2(zr, zi);
-        const unsigned pt = PF ? lds_fetch_wait() : 0u;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           const unsigned o = k * K::NT;
+          const unsigned vk = xi_off(k);
           T er, ei;
           cmul(pxr, pxi, py[2 * k], py[2 * k + 1], er, ei);
           T xr, xi;
           cmul(zr[k], zi[k], er, -ei, xr, xi);
-          const T pr0 = PF ? pf[PF ? o + pt : 0] : bld<T>(rp, vo, (fr + o) * S);
-          const T pi0 = bld<T>(rp, vo, (fi + o) * S);
+          const T pr0 = bld<T>(rp, vk, (fr + o) * S);
+          const T pi0 = bld<T>(rp, vk, (fi + o) * S);
           xr += m != 0 ? pr0 : (T)0;
           xi += m != 0 ? pi0 : (T)0;
-          bst<T>(rp, xr, vo, (fr + o) * S);
-          bst<T>(rp, xi, vo, (fi + o) * S);
+          bst<T>(rp, xr, vk, (fr + o) * S);
+          bst<T>(rp, xi, vk, (fi + o) * S);
           if (k % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
       } else if (m == 0) {
         // no partner spectrum (unpaired kernel, or a single node)
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          bst<T>(rp, (T)0, vo, (fr + k * K::NT) * S);
-          bst<T>(rp, (T)0, vo, (fi + k * K::NT) * S);
+          const unsigned vk = xi_off(k);
+          bst<T>(rp, (T)0, vk, (fr + k * K::NT) * S);
+          bst<T>(rp, (T)0, vk, (fi + k * K::NT) * S);
         }
       }
     }
@@ -669,20 +681,28 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
 
 // Real-space P-grid fields of C, elementwise: sums the per-j partials of I_3
 // and assembles the Pauli components (C_c + pi (A + B + Cq), see k_combine)
-// into i3sum[cell][mu]; sums the partner-node spectra of I_3 into i3ps.
-template <typename T>
-__global__ void k_assemble(DevPlan<T> d, int ncells, int fsz) {
+// into i3sum[cell][mu]; sums the partner-node spectra of I_3 into i3ps on
+// Xi (the only entries k_i3 writes and k_combine reads; 0 elsewhere).
+template <typename T, int P, int E>
+__global__ void k_assemble(DevPlan<T> d, int ncells) {
+  using Eng = Fft2<T, P, E>;
+  constexpr int fsz = P * P;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (size_t)ncells * fsz) return;
   const size_t cell = idx / fsz, e = idx % fsz;
   const size_t per = (size_t)4 * fsz;
+  // col spec position e = k NT + t: frequency (kx, ky) = (t / TPR, k + E bitrev(q))
+  const int t = (int)(e % Eng::NT), kk = (int)(e / Eng::NT);
+  const int bx = centered<P>(t / Eng::TPR);
+  const int by = centered<P>(kk + E * bitrev_rt(Eng::lane_label(t % Eng::TPR), Eng::LB));
+  const bool on_xi = bx > -P / 4 && bx < P / 4 && by > -P / 4 && by < P / 4;
   const T* o3 = d.i3o + cell * d.J * per + e;
   const T* p3 = d.i3p + cell * d.J * per + e;
   T b[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
   for (int j = 0; j < d.J; ++j)
     for (int nu = 0; nu < 4; ++nu) {
       b[nu] += o3[(size_t)j * per + (size_t)nu * fsz];
-      q[nu] += p3[(size_t)j * per + (size_t)nu * fsz];
+      if (on_xi) q[nu] += p3[(size_t)j * per + (size_t)nu * fsz];
     }
   T* ps = d.i3ps + cell * per + e;
   for (int nu = 0; nu < 4; ++nu) ps[(size_t)nu * fsz] = q[nu];

@@ -454,7 +454,8 @@ bool build_adjoint(qb_plan_s* pl) {
          pl->alloc_adj(&pl->tsb, C * 2 * qb::kTermsVjpTasks * FSZ * b) &&
          pl->alloc_adj(&pl->i3g, C * J * 8 * FSZ * b) && pl->alloc_adj(&pl->i3sb, C * J * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->gsum, C * 8 * FSZ * b) && pl->alloc_adj(&pl->i3t, C * J * 4 * FSZ * b) &&
-         pl->alloc_adj(&pl->lamh, C * 4 * FSZ * b) &&
+         pl->alloc_adj(&pl->lamh, C * 4 * FSZ * b) && pl->alloc_adj(&pl->fwa, C * 14 * FSZ * b) &&
+         pl->alloc_adj(&pl->spart, C * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
          pl->alloc_adj((void**)&pl->lflux, 2 * sizeof(double));
 }

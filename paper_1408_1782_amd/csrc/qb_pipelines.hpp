@@ -30,7 +30,7 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, 
                        dim3(NT), 0, s, d, ncells);
   pl->end(id, s);
   const size_t nel = (size_t)ncells * P * P;
-  hipLaunchKernelGGL((qb::k_assemble<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
+  hipLaunchKernelGGL((qb::k_assemble<T, P, E>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells);
   id = pl->begin(QB_K_COMBINE, s);
   hipLaunchKernelGGL((qb::k_combine<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, c, cell0);
   pl->end(id, s);
@@ -46,14 +46,13 @@ bool collision_vjp_pipeline(qb_plan_s* pl, const T* w, const T* lam, T* out, int
   int id = pl->begin(QB_K_DFT_IN, s);
   hipLaunchKernelGGL((qb::k_dft_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, w, cell0);
   pl->end(id, s);
-  id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(ncells * 8), dim3(NT), 0, s, d, ncells);
-  pl->end(id, s);
+  // the forward I_1 / I_4 / I_2 fields are formed inside k_terms_vjp
   id = pl->begin(QB_K_ADJOINT, s);
   hipLaunchKernelGGL((qb::k_lam_in<T, P, E>), dim3(ncells), dim3(NT), 0, s, d, lam, cell0);
   const size_t nel = (size_t)ncells * P * P;
-  hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P);
+  hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P, 0);
   hipLaunchKernelGGL((qb::k_terms_vjp<T, P, E>), dim3(ncells * qb::kTermsVjpTasks), dim3(NT), 0, s, d);
+  hipLaunchKernelGGL((qb::k_assemble_vjp<T>), dim3(blocks(nel, 256)), dim3(256), 0, s, d, ncells, P * P, 1);
   pl->end(id, s);
   id = pl->begin(QB_K_I3_ADJOINT, s);
   if (pl->vjp_variant == 1)

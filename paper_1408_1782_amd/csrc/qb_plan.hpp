@@ -80,6 +80,7 @@ struct qb_plan_s {
   bool adjoint = false;
   void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
        *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
+  void *fwa = nullptr, *spart = nullptr;
   void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
        *cg = nullptr, *g0 = nullptr, *ext = nullptr;
   double* lflux = nullptr;
@@ -178,6 +179,8 @@ inline DevPlan<T> devplan(qb_plan_s* pl, int tab) {
   d.i3g = (T*)pl->i3g;
   d.i3sb = (T*)pl->i3sb;
   d.gsum = (T*)pl->gsum;
+  d.fwa = (T*)pl->fwa;
+  d.spart = (T*)pl->spart;
   d.i3t = (T*)pl->i3t;
   d.lamh = (T*)pl->lamh;
   return d;
