@@ -123,7 +123,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_lam_in(DevPlan<T> d, co
 //   acot[12..15] the explicit dependence of r on w_mu
 // Part 0 writes acot[0..11], which need only lam and w; part 1 writes
 // acot[12..15] from the forward fields g, y (terms[0..6]) and S (the sum
-// of its per-component parts spart[0..3]), which k_terms_vjp produces.
+// of its per-component parts terms[7..10]), which k_terms_vjp produces.
 template <typename T>
 __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz, int part) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -151,11 +151,10 @@ __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz, int part) {
     o[11 * fsz] = tp * l3;
     return;
   }
-  const T* tr = d.terms + cell * 8 * fsz + e;
-  const T* sp = d.spart + cell * 4 * fsz + e;
+  const T* tr = d.terms + cell * kTermPlanes * fsz + e;
   const T g1 = tr[0], g2 = tr[fsz], g3 = tr[2 * fsz];
   const T y0 = tr[3 * fsz], y1 = tr[4 * fsz], y2 = tr[5 * fsz], y3 = tr[6 * fsz];
-  const T Sv = sp[0] + sp[fsz] + sp[2 * fsz] + sp[3 * fsz];
+  const T Sv = (tr[7 * fsz] + tr[8 * fsz]) + (tr[9 * fsz] + tr[10 * fsz]);
   const T q = pi * (-two * Sv + two * y0);
   o[12 * fsz] = q * l0 - tp * (y1 * l1 + y2 * l2 + y3 * l3);
   o[13 * fsz] = -tp * y1 * l0 + q * l1 - two * g3 * l2 + two * g2 * l3;
@@ -167,21 +166,28 @@ __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz, int part) {
 // Transpose of k_terms, one workgroup per (cell, task), fused with the
 // forward fields the transpose of the assembly needs (k_terms computes
 // the same fields; running both here shares their inner transforms).
-// Tasks 0..6 (I_1 with l = task + 1, I_4 with g = task - 3):
+// Tasks 0..6 (I_1 with l = task + 1, I_4 with g = task - 3), per direction j:
 //   forward  a_j = inv2(in_j w_hat_g), c_j = fwd2(f0 a_j), field = Re inv2(sum_j out_j c_j)
-//   reverse  d = conj(F) field_bar;  b_j = F(out_j d);
+//   reverse  b_j = F(out_j d) with d = conj(F) field_bar;
 //            f0_bar += Re(a_j b_j);  w_hat_g_bar += in_j conj(F)(f0 b_j)
-//   (four transforms per j: b_j, a_j, c_j and the last one; field goes to
-//   terms[task])
-// Tasks 7..10 (I_2, one Pauli component mu = task - 7 each, so that every
-// task does three transforms per j):
+// The tables in_j, out_j are real and have one parity in k (odd for I_1,
+// even for I_4), and w_hat_g, field_bar are spectra of real fields, so
+// a_j, b_j are real up to a fixed phase.  Two directions j, j+1 therefore
+// share every transform (dir_pair gives the complex coefficients): one
+// transform yields a_j + i a_j+1 (up to the phase), one the pair's forward
+// contribution, one b_j + i b_j+1, and one the pair's cotangent H, whose
+// Hermitian part (H(k) + conj H(-k)) / 2 is the cotangent of w_hat_g;
+// k_grad_pre takes that part.
+// Tasks 7..10 (I_2, one Pauli component mu = task - 7 each):
 //            S = sum_j sum_mu e_mu A_j,mu B_j,mu with A + iB = inv2(w_hat_mu (psi_j + i psi'_j)):
 //            w_hat_mu_bar += psi_j conj(F)(S_bar e_mu B) + psi'_j conj(F)(S_bar e_mu A)
-//   (the component's share sum_j e_mu A B of S goes to spart[mu])
+//   The two real products go through one transform Z = fwd2(S_bar e_mu (B + iA));
+//   (psi_j + i psi'_j) conj(Z) has the cotangent as its Hermitian part.
+//   (the component's share sum_j e_mu A B of S goes to terms[task])
 // The field cotangents (acot[0..7]) depend only on lam and w, so they are
 // ready before this kernel; the dependence of the assembly on the fields
 // themselves (acot[12..15]) is formed after it.
-constexpr int kTermsVjpTasks = 11;
+constexpr int kTermsVjpTasks = kTermPlanes;
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d) {
   using K = Kern<T, P, E>;
@@ -195,20 +201,22 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
   const rsrc_t ra = mkbuf(d.acot + (size_t)cell * 16 * K::FSZ, 16 * K::FSZ);
-  const rsrc_t rt = mkbuf(d.tsb + ((size_t)cell * kTermsVjpTasks + task) * 2 * K::FSZ, 2 * K::FSZ);
   const size_t tabn = (size_t)d.J * K::FSZ;
   if (task < 7) {
     const int g = task < 3 ? task + 1 : task - 3;
-    const rsrc_t rin = mkbuf(task < 3 ? d.phip : d.psip, tabn);
-    const rsrc_t rout = mkbuf(task < 3 ? d.Kt : d.psiw, tabn);
+    const bool odd = task < 3;
+    const rsrc_t rt = mkbuf(d.tsb + ((size_t)cell * kTermsVjpTasks + task) * 2 * K::FSZ, 2 * K::FSZ);
+    const rsrc_t rin = mkbuf(odd ? d.phip : d.psip, tabn);
+    const rsrc_t rout = mkbuf(odd ? d.Kt : d.psiw, tabn);
     const rsrc_t rd = mkbuf(d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
     const rsrc_t rc = mkbuf(d.fwa + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
     const rsrc_t rf = mkbuf(d.gf0 + ((size_t)cell * 7 + task) * K::FSZ, K::FSZ);
     const rsrc_t rg = mkbuf(d.gspec + ((size_t)cell * 11 + task) * 2 * K::FSZ, 2 * K::FSZ);
-    const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * 8 + task) * K::FSZ, K::FSZ);
+    const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * kTermPlanes + task) * K::FSZ, K::FSZ);
     const unsigned fg = 2 * g * K::FSZ;
+    const T sgn = odd ? (T)-1 : (T)1;
     {
-      // d = conj(F) field_bar = conj(fwd2(field_bar)) for the real field_bar
+      // D = F field_bar for the real field_bar (d = conj D)
       T zr[E], zi[E];
 #pragma unroll
       for (int n = 0; n < E; ++n) {
@@ -219,35 +227,38 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         bst<T>(rd, zr[k], vo, (k * K::NT) * S);
-        bst<T>(rd, -zi[k], vo, (K::FSZ + k * K::NT) * S);
+        bst<T>(rd, zi[k], vo, (K::FSZ + k * K::NT) * S);
       }
     }
 #pragma unroll 1
-    for (int j = 0; j < d.J; ++j) {
-      const unsigned tj = j * K::FSZ;
+    for (int j = 0; j < d.J; j += 2) {
+      const unsigned t1 = j * K::FSZ, t2 = t1 + K::FSZ;
       T zr[E], zi[E];
-      // b_j = F(out_j d) = conj(inv2(conj(out_j d)))
+      // B = inv2(cb D) = b_j + i b_j+1 up to the phase
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rout, vo, (tj + o) * S);
-        zr[k] = a * bld<T>(rd, vo, o * S);
-        zi[k] = -a * bld<T>(rd, vo, (K::FSZ + o) * S);
+        const T o1 = bld<T>(rout, vo, (t1 + o) * S), o2 = bld<T>(rout, vo, (t2 + o) * S);
+        const T cr = odd ? -o2 : o1, ci = odd ? o1 : o2;
+        const T dr = bld<T>(rd, vo, o * S), di = bld<T>(rd, vo, (K::FSZ + o) * S);
+        zr[k] = cr * dr - ci * di;
+        zi[k] = cr * di + ci * dr;
       }
       eng.inv2(zr, zi);
 #pragma unroll
       for (int n = 0; n < E; ++n) {
-        // b_j = conj of the transform
         bst<T>(rt, zr[n], vo, (n * K::NT) * S);
-        bst<T>(rt, -zi[n], vo, (K::FSZ + n * K::NT) * S);
+        bst<T>(rt, zi[n], vo, (K::FSZ + n * K::NT) * S);
       }
-      // a_j = inv2(in_j w_hat_g)
+      // A = inv2(cin w_hat_g) = a_j + i a_j+1 up to the phase
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rin, vo, (tj + o) * S);
-        zr[k] = bld<T>(rs, vo, (fg + o) * S) * a;
-        zi[k] = bld<T>(rs, vo, (fg + K::FSZ + o) * S) * a;
+        const T i1 = bld<T>(rin, vo, (t1 + o) * S), i2 = bld<T>(rin, vo, (t2 + o) * S);
+        const T cr = odd ? i2 : i1, ci = odd ? -i1 : i2;
+        const T sr = bld<T>(rs, vo, (fg + o) * S), si = bld<T>(rs, vo, (fg + K::FSZ + o) * S);
+        zr[k] = sr * cr - si * ci;
+        zi[k] = sr * ci + si * cr;
       }
       eng.inv2(zr, zi);
 #pragma unroll
@@ -255,20 +266,21 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         const unsigned o = n * K::NT;
         const T br = bld<T>(rt, vo, o * S), bi = bld<T>(rt, vo, (K::FSZ + o) * S);
         const T f0 = bld<T>(rw, vo, (4 * K::FSZ + o) * S);
-        T fb = zr[n] * br - zi[n] * bi;
+        T fb = sgn * (zr[n] * br + zi[n] * bi);
         if (j != 0) fb += bld<T>(rf, vo, o * S);
         bst<T>(rf, fb, vo, o * S);
-        // forward: f0 a_j, transformed by fwd2 below
+        // forward: f0 A, transformed by fwd2 below
         zr[n] *= f0;
         zi[n] *= f0;
       }
-      // c_j = fwd2(f0 a_j); the forward accumulator gets out_j c_j
+      // the pair's forward contribution cout fwd2(f0 A)
       eng.fwd2(zr, zi);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rout, vo, (tj + o) * S);
-        T ar = a * zr[k], ai = a * zi[k];
+        const T o1 = bld<T>(rout, vo, (t1 + o) * S), o2 = bld<T>(rout, vo, (t2 + o) * S);
+        const T cr = odd ? o2 : o1, ci = odd ? o1 : -o2;
+        T ar = cr * zr[k] - ci * zi[k], ai = cr * zi[k] + ci * zr[k];
         // read at j = 0 too (not yet written) and dropped by a select
         const T pr = bld<T>(rc, vo, o * S), pi = bld<T>(rc, vo, (K::FSZ + o) * S);
         ar += j != 0 ? pr : (T)0;
@@ -276,20 +288,21 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         bst<T>(rc, ar, vo, o * S);
         bst<T>(rc, ai, vo, (K::FSZ + o) * S);
       }
-      // conj(f0 b_j), transformed by fwd2 below
+      // Z = fwd2(f0 B);  H += cw conj(Z)
 #pragma unroll
       for (int n = 0; n < E; ++n) {
         const unsigned o = n * K::NT;
         const T f0 = bld<T>(rw, vo, (4 * K::FSZ + o) * S);
         zr[n] = f0 * bld<T>(rt, vo, o * S);
-        zi[n] = -f0 * bld<T>(rt, vo, (K::FSZ + o) * S);
+        zi[n] = f0 * bld<T>(rt, vo, (K::FSZ + o) * S);
       }
       eng.fwd2(zr, zi);
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rin, vo, (tj + o) * S);
-        T xr = a * zr[k], xi = -a * zi[k];
+        const T i1 = bld<T>(rin, vo, (t1 + o) * S), i2 = bld<T>(rin, vo, (t2 + o) * S);
+        const T cr = odd ? -i2 : i1, ci = odd ? i1 : i2;
+        T xr = cr * zr[k] + ci * zi[k], xi = ci * zr[k] - cr * zi[k];
         if (j != 0) {
           xr += bld<T>(rg, vo, o * S);
           xi += bld<T>(rg, vo, (K::FSZ + o) * S);
@@ -298,7 +311,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
         bst<T>(rg, xi, vo, (K::FSZ + o) * S);
       }
     }
-    // the forward field: Re inv2(sum_j out_j c_j)
+    // the forward field: Re inv2(sum over pairs)
     T zr[E], zi[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -314,59 +327,46 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d)
     const rsrc_t rps = mkbuf(d.psi, tabn);
     const rsrc_t rpp = mkbuf(d.psip, tabn);
     const int mu = task - 7;
-    const rsrc_t rsp = mkbuf(d.spart + ((size_t)cell * 4 + mu) * K::FSZ, K::FSZ);
+    const unsigned fm = 2 * mu * K::FSZ;
+    const rsrc_t rg = mkbuf(d.gspec + ((size_t)cell * 11 + 7 + mu) * 2 * K::FSZ, 2 * K::FSZ);
+    const rsrc_t rsp = mkbuf(d.terms + ((size_t)cell * kTermPlanes + task) * K::FSZ, K::FSZ);
+    const T e = mu == 0 ? wj : -wj;
     T Sacc[E];
 #pragma unroll
     for (int n = 0; n < E; ++n) Sacc[n] = 0;
 #pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
       const unsigned tj = j * K::FSZ;
-      {
-        const unsigned fm = 2 * mu * K::FSZ;
-        const rsrc_t rg = mkbuf(d.gspec + ((size_t)cell * 11 + 7 + mu) * 2 * K::FSZ, 2 * K::FSZ);
-        T zr[E], zi[E];
+      T zr[E], zi[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const unsigned o = k * K::NT;
-          const T ar = bld<T>(rs, vo, (fm + o) * S), ai = bld<T>(rs, vo, (fm + K::FSZ + o) * S);
-          const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
-          zr[k] = ar * a - ai * b;
-          zi[k] = ai * a + ar * b;
+      for (int k = 0; k < E; ++k) {
+        const unsigned o = k * K::NT;
+        const T ar = bld<T>(rs, vo, (fm + o) * S), ai = bld<T>(rs, vo, (fm + K::FSZ + o) * S);
+        const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
+        zr[k] = ar * a - ai * b;
+        zi[k] = ai * a + ar * b;
+      }
+      eng.inv2(zr, zi);  // (A, B)
+#pragma unroll
+      for (int n = 0; n < E; ++n) {
+        Sacc[n] += e * zr[n] * zi[n];  // the forward accumulator's share
+        const T sb = e * bld<T>(ra, vo, (7 * K::FSZ + n * K::NT) * S);
+        const T A = zr[n];
+        zr[n] = sb * zi[n];  // S_bar e B
+        zi[n] = sb * A;      // S_bar e A
+      }
+      eng.fwd2(zr, zi);
+#pragma unroll
+      for (int k = 0; k < E; ++k) {
+        const unsigned o = k * K::NT;
+        const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
+        T xr = a * zr[k] + b * zi[k], xi = b * zr[k] - a * zi[k];
+        if (j != 0) {
+          xr += bld<T>(rg, vo, o * S);
+          xi += bld<T>(rg, vo, (K::FSZ + o) * S);
         }
-        eng.inv2(zr, zi);  // (A, B)
-        const T e = mu == 0 ? wj : -wj;
-#pragma unroll
-        for (int n = 0; n < E; ++n) {
-          Sacc[n] += e * zr[n] * zi[n];  // the forward accumulator's share
-          const T sb = e * bld<T>(ra, vo, (7 * K::FSZ + n * K::NT) * S);
-          bst<T>(rt, sb * zr[n], vo, (n * K::NT) * S);  // B_bar = S_bar e A
-          zr[n] = sb * zi[n];                          // A_bar = S_bar e B
-          zi[n] = 0;
-        }
-#pragma unroll 1
-        for (int half = 0; half < 2; ++half) {
-          if (half == 1) {
-#pragma unroll
-            for (int n = 0; n < E; ++n) {
-              zr[n] = bld<T>(rt, vo, (n * K::NT) * S);
-              zi[n] = 0;
-            }
-          }
-          eng.fwd2(zr, zi);
-          const rsrc_t rm = half == 0 ? rps : rpp;
-#pragma unroll
-          for (int k = 0; k < E; ++k) {
-            const unsigned o = k * K::NT;
-            const T a = bld<T>(rm, vo, (tj + o) * S);
-            T xr = a * zr[k], xi = -a * zi[k];
-            if (j != 0 || half != 0) {
-              xr += bld<T>(rg, vo, o * S);
-              xi += bld<T>(rg, vo, (K::FSZ + o) * S);
-            }
-            bst<T>(rg, xr, vo, o * S);
-            bst<T>(rg, xi, vo, (K::FSZ + o) * S);
-          }
-        }
+        bst<T>(rg, xr, vo, o * S);
+        bst<T>(rg, xi, vo, (K::FSZ + o) * S);
       }
     }
 #pragma unroll
@@ -675,18 +675,20 @@ __global__ void k_grad_pre(DevPlan<T> d, int ncells, int fsz) {
     const int pr = (q - 4) / 2, im = (q - 4) % 2;
     const int ma = 2 * pr, mb = 2 * pr + 1;
     // task slots of gspec: I_1 (mu >= 1) at mu - 1, I_4 at 3 + mu, I_2 at 7 + mu
+    // k_terms_vjp leaves H with the cotangent (H(k) + conj H(-k)) / 2
     const T* gs = d.gspec + cell * 22 * fsz + e;
+    const T* gn = d.gspec + cell * 22 * fsz + d.negk[e];
     T ar = 0, ai = 0, br = 0, bi = 0;
     const int sa[3] = {ma - 1, 3 + ma, 7 + ma}, sb[3] = {mb - 1, 3 + mb, 7 + mb};
     for (int t = 0; t < 3; ++t) {
       if (sa[t] >= 0) {
-        ar += gs[(size_t)(2 * sa[t]) * fsz];
-        ai += gs[(size_t)(2 * sa[t] + 1) * fsz];
+        ar += gs[(size_t)(2 * sa[t]) * fsz] + gn[(size_t)(2 * sa[t]) * fsz];
+        ai += gs[(size_t)(2 * sa[t] + 1) * fsz] - gn[(size_t)(2 * sa[t] + 1) * fsz];
       }
-      br += gs[(size_t)(2 * sb[t]) * fsz];
-      bi += gs[(size_t)(2 * sb[t] + 1) * fsz];
+      br += gs[(size_t)(2 * sb[t]) * fsz] + gn[(size_t)(2 * sb[t]) * fsz];
+      bi += gs[(size_t)(2 * sb[t] + 1) * fsz] - gn[(size_t)(2 * sb[t] + 1) * fsz];
     }
-    a += im == 0 ? ar - bi : ai + br;
+    a += (T)0.5 * (im == 0 ? ar - bi : ai + br);
   }
   d.gsum[cell * per + r] = a;
 }

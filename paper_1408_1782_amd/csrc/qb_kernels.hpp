@@ -45,13 +45,14 @@ struct DevPlan {
   const T* psip;   // psi_R(b . theta_j^perp)                   (I_2, I_4 inner)
   const T* psiw;   // (pi/J) psi_R(b . theta_j) / P^2           (I_4 outer)
   const T* psips;  // psi_R(b . theta_j^perp) / P^2             (I_3 multiplier)
+  const unsigned* negk;  // [P*P] col spec position of -k for the position of k
   const T* phx;    // [J][M][P][2] exp(i pi rho_m theta_j,x b_x / L)
   const T* phy;    // [J][M][P][2] exp(i pi rho_m theta_j,y b_y / L)
   const T* wm;     // [M] (pi/J) w_m
   // work buffers
   T* spec;   // [cells][4][2][P*P]  w_hat_mu, col spec
   T* wP;     // [cells][5][P*P]     w_mu and f0 = 2 w0 - 1 on the P grid, row real
-  T* terms;  // [cells][8][P*P]     I_1 (3), I_4 (4), I_2 (1) real-space fields
+  T* terms;  // [cells][11][P*P]    I_1 (3), I_4 (4), I_2 (one per Pauli component) real-space fields
   T* acc;    // [cells][7][2][P*P]  spectral accumulators of the I_1 / I_4 tasks
   T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
   T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
@@ -71,7 +72,6 @@ struct DevPlan {
   T* lamh;   // [cells][4][P*P]     spectrum of lamP, packed pairs, col spec
   T* gsum;   // [cells][8][P*P]     gathered cotangents (k_grad_pre)
   T* fwa;    // [cells][7][2][P*P]  spectral accumulators of the forward I_1 / I_4 fields in k_terms_vjp
-  T* spart;  // [cells][4][P*P]     I_2 accumulator S split by Pauli component (k_terms_vjp)
 };
 
 // ------------------------------------------------------------------ helpers
@@ -284,8 +284,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_dft_in(DevPlan<T> d, co
 // task 0..2: I_1[f0, w_l, .] (l = task + 1), hoisted outer kernel K_j'
 // task 3..6: I_4[f0, w_g, .] (g = task - 3)
 // Both: sum_j outer_j(p) FFT( f0 * IFFT(inner_j w_hat_g) ), then one IFFT.
-// task 7   : I_2 accumulator S = sum_j (pi/J) sum_mu eta_mu
+// task 7..10: I_2 accumulator S = sum_mu S_mu, one Pauli component
+//            mu = task - 7 per task: S_mu = sum_j (pi/J) eta_mu
 //            IFFT(psi_j w_hat_mu) IFFT(psi'_j w_hat_mu)   (real space)
+constexpr int kTermPlanes = 11;
 template <typename T, int P, int E>
 __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int ncells) {
   using K = Kern<T, P, E>;
@@ -295,13 +297,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int
   setup(eng, smem, d.tw);
   // one (cell, task) per workgroup, or grid-stride when persistent
 #pragma unroll 1
-  for (int pt = blockIdx.x; pt < ncells * 8; pt += gridDim.x) {
-  const int cell = pt / 8;
-  const int task = pt % 8;
+  for (int pt = blockIdx.x; pt < ncells * kTermPlanes; pt += gridDim.x) {
+  const int cell = pt / kTermPlanes;
+  const int task = pt % kTermPlanes;
   const unsigned vo = threadIdx.x * S;
   const rsrc_t rs = mkbuf(d.spec + (size_t)cell * 8 * K::FSZ, 8 * K::FSZ);
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
-  const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * 8 + task) * K::FSZ, K::FSZ);
+  const rsrc_t ro = mkbuf(d.terms + ((size_t)cell * kTermPlanes + task) * K::FSZ, K::FSZ);
   const size_t tabn = (size_t)d.J * K::FSZ;
   if (task < 7) {
     const int g = task < 3 ? task + 1 : task - 3;
@@ -309,16 +311,26 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int
     const rsrc_t rout = mkbuf(task < 3 ? d.Kt : d.psiw, tabn);
     const rsrc_t ra = mkbuf(d.acc + ((size_t)cell * 7 + task) * 2 * K::FSZ, 2 * K::FSZ);
     const unsigned fg = 2 * g * K::FSZ;
+    // in_j, out_j are real with one parity in k (odd for I_1, even for
+    // I_4) and w_hat_g is the spectrum of a real field, so a_j is real up
+    // to a fixed phase: directions j, j+1 share both transforms, with
+    // coefficients (i_j + i i_j+1, o_j - i o_j+1) for even tables and
+    // (i_j+1 - i i_j, o_j+1 + i o_j) for odd ones.  The real part of the
+    // final inverse transform is the field; the cross terms the sharing
+    // adds are imaginary there.
+    const bool odd = task < 3;
 #pragma unroll 1
-    for (int j = 0; j < d.J; ++j) {
+    for (int j = 0; j < d.J; j += 2) {
       T zr[E], zi[E];
-      const unsigned tj = j * K::FSZ;
+      const unsigned t1 = j * K::FSZ, t2 = t1 + K::FSZ;
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rin, vo, (tj + o) * S);
-        zr[k] = bld<T>(rs, vo, (fg + o) * S) * a;
-        zi[k] = bld<T>(rs, vo, (fg + K::FSZ + o) * S) * a;
+        const T i1 = bld<T>(rin, vo, (t1 + o) * S), i2 = bld<T>(rin, vo, (t2 + o) * S);
+        const T cr = odd ? i2 : i1, ci = odd ? -i1 : i2;
+        const T sr = bld<T>(rs, vo, (fg + o) * S), si = bld<T>(rs, vo, (fg + K::FSZ + o) * S);
+        zr[k] = sr * cr - si * ci;
+        zi[k] = sr * ci + si * cr;
       }
       eng.inv2(zr, zi);
 #pragma unroll
@@ -331,8 +343,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int
 #pragma unroll
       for (int k = 0; k < E; ++k) {
         const unsigned o = k * K::NT;
-        const T a = bld<T>(rout, vo, (tj + o) * S);
-        T ar = a * zr[k], ai = a * zi[k];
+        const T o1 = bld<T>(rout, vo, (t1 + o) * S), o2 = bld<T>(rout, vo, (t2 + o) * S);
+        const T cr = odd ? o2 : o1, ci = odd ? o1 : -o2;
+        T ar = cr * zr[k] - ci * zi[k], ai = cr * zi[k] + ci * zr[k];
         // read at j = 0 too (not yet written) and dropped by a select
         const T pr = bld<T>(ra, vo, o * S), pi = bld<T>(ra, vo, (K::FSZ + o) * S);
         ar += j != 0 ? pr : (T)0;
@@ -352,33 +365,31 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int
 #pragma unroll
     for (int n = 0; n < E; ++n) bst<T>(ro, zr[n], vo, (n * K::NT) * S);
   } else {
+    // one Pauli component per task: S_mu = sum_j e_mu A_j,mu B_j,mu
+    const int mu = task - 7;
+    const unsigned fm = 2 * mu * K::FSZ;
+    const T e = (T)(kPi / d.J) * (mu == 0 ? (T)1 : (T)-1);
     T Sacc[E];
 #pragma unroll
     for (int n = 0; n < E; ++n) Sacc[n] = 0;
-    const T wj = (T)(kPi / d.J);
     const rsrc_t rps = mkbuf(d.psi, tabn);
     const rsrc_t rpp = mkbuf(d.psip, tabn);
 #pragma unroll 1
     for (int j = 0; j < d.J; ++j) {
       const unsigned tj = j * K::FSZ;
-#pragma unroll 1
-      for (int mu = 0; mu < 4; ++mu) {
-        const unsigned fm = 2 * mu * K::FSZ;
-        T zr[E], zi[E];
+      T zr[E], zi[E];
 #pragma unroll
-        for (int k = 0; k < E; ++k) {
-          const unsigned o = k * K::NT;
-          const T ar = bld<T>(rs, vo, (fm + o) * S), ai = bld<T>(rs, vo, (fm + K::FSZ + o) * S);
-          const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
-          // w_hat psi + i w_hat psi'
-          zr[k] = ar * a - ai * b;
-          zi[k] = ai * a + ar * b;
-        }
-        eng.inv2(zr, zi);
-        const T e = mu == 0 ? wj : -wj;
-#pragma unroll
-        for (int n = 0; n < E; ++n) Sacc[n] += e * zr[n] * zi[n];
+      for (int k = 0; k < E; ++k) {
+        const unsigned o = k * K::NT;
+        const T ar = bld<T>(rs, vo, (fm + o) * S), ai = bld<T>(rs, vo, (fm + K::FSZ + o) * S);
+        const T a = bld<T>(rps, vo, (tj + o) * S), b = bld<T>(rpp, vo, (tj + o) * S);
+        // w_hat psi + i w_hat psi'
+        zr[k] = ar * a - ai * b;
+        zi[k] = ai * a + ar * b;
       }
+      eng.inv2(zr, zi);
+#pragma unroll
+      for (int n = 0; n < E; ++n) Sacc[n] += e * zr[n] * zi[n];
     }
 #pragma unroll
     for (int n = 0; n < E; ++n) bst<T>(ro, Sacc[n], vo, (n * K::NT) * S);
@@ -707,11 +718,11 @@ __global__ void k_assemble(DevPlan<T> d, int ncells) {
   T* ps = d.i3ps + cell * per + e;
   for (int nu = 0; nu < 4; ++nu) ps[(size_t)nu * fsz] = q[nu];
   const T* wp = d.wP + cell * 5 * fsz + e;
-  const T* tr = d.terms + cell * 8 * fsz + e;
+  const T* tr = d.terms + cell * kTermPlanes * fsz + e;
   const T w0 = wp[0], w1 = wp[fsz], w2 = wp[2 * fsz], w3 = wp[3 * fsz];
   const T g1 = tr[0], g2 = tr[fsz], g3 = tr[2 * fsz];
   const T y0 = tr[3 * fsz], y1 = tr[4 * fsz], y2 = tr[5 * fsz], y3 = tr[6 * fsz];
-  const T Sv = tr[7 * fsz];
+  const T Sv = (tr[7 * fsz] + tr[8 * fsz]) + (tr[9 * fsz] + tr[10 * fsz]);
   const T pi = (T)kPi, two = (T)2;
   T* r = d.i3sum + cell * per + e;
   // A: 2 <w3, w4>_eta (1 - W1); B: -2 <w3, w4>_eta (eta w2).sigma;

@@ -159,7 +159,7 @@ inline size_t colspec_index(int kx, int ky, int E, int TPR, int NT) {
 inline int centered_h(int k, int P) { return k < P / 2 ? k : k - P; }
 
 // Reserve the workspace of one tile shape's table set (twiddles, phi',
-// K, psi, psi', weighted psi, psi' / P^2).
+// K, psi, psi', weighted psi, psi' / P^2, the position of -k).
 template <typename T>
 bool reserve_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
   const size_t P = pl->P, J = pl->prob.J, FSZ = P * P, b = sizeof(T);
@@ -167,7 +167,7 @@ bool reserve_layout_tables(qb_plan_s* pl, int E, qb_plan_s::TabSet& ts) {
   ts.built = false;
   return pl->alloc(&ts.tw, 2 * P * b) && pl->alloc(&ts.phip, J * FSZ * b) && pl->alloc(&ts.Kt, J * FSZ * b) &&
          pl->alloc(&ts.psi, J * FSZ * b) && pl->alloc(&ts.psip, J * FSZ * b) && pl->alloc(&ts.psiw, J * FSZ * b) &&
-         pl->alloc(&ts.psips, J * FSZ * b);
+         pl->alloc(&ts.psips, J * FSZ * b) && pl->alloc(&ts.negk, FSZ * sizeof(unsigned));
 }
 
 // Compute the table set of tile shape ts.E in float64 and copy it into its
@@ -223,8 +223,14 @@ bool fill_layout_tables(qb_plan_s* pl, qb_plan_s::TabSet& ts) {
       }
     }
   }
+  // col spec position of -k (mod P) for each position of k
+  std::vector<unsigned> negk(FSZ);
+  for (int kx = 0; kx < P; ++kx)
+    for (int ky = 0; ky < P; ++ky)
+      negk[colspec_index(kx, ky, E, TPR, NT)] = (unsigned)colspec_index((P - kx) % P, (P - ky) % P, E, TPR, NT);
   ts.built = put<T>(ts.tw, tw) && put<T>(ts.phip, phip) && put<T>(ts.Kt, Kt) && put<T>(ts.psi, psi) &&
-             put<T>(ts.psip, psip) && put<T>(ts.psiw, psiw) && put<T>(ts.psips, psips);
+             put<T>(ts.psip, psip) && put<T>(ts.psiw, psiw) && put<T>(ts.psips, psips) &&
+             hip_ok(hipMemcpy(ts.negk, negk.data(), FSZ * sizeof(unsigned), hipMemcpyHostToDevice), "hipMemcpy");
   return ts.built;
 }
 
@@ -411,7 +417,7 @@ template <typename T>
 bool carve_collision(Arena& a, const qb_plan_s* pl, size_t C, CollBufs& b) {
   const size_t FSZ = (size_t)pl->P * pl->P, J = pl->prob.J, t = sizeof(T);
   return a.take(&b.i3s, C * J * 4 * FSZ * t) && a.take(&b.spec, C * 8 * FSZ * t) &&
-         a.take(&b.wP, C * 5 * FSZ * t) && a.take(&b.terms, C * 8 * FSZ * t) && a.take(&b.acc, C * 14 * FSZ * t) &&
+         a.take(&b.wP, C * 5 * FSZ * t) && a.take(&b.terms, C * qb::kTermPlanes * FSZ * t) && a.take(&b.acc, C * 14 * FSZ * t) &&
          a.take(&b.i3o, C * J * 4 * FSZ * t) && a.take(&b.i3sum, C * 4 * FSZ * t) &&
          a.take(&b.i3p, C * J * 4 * FSZ * t) && a.take(&b.i3ps, C * 4 * FSZ * t);
 }
@@ -455,7 +461,6 @@ bool build_adjoint(qb_plan_s* pl) {
          pl->alloc_adj(&pl->i3g, C * J * 8 * FSZ * b) && pl->alloc_adj(&pl->i3sb, C * J * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->gsum, C * 8 * FSZ * b) && pl->alloc_adj(&pl->i3t, C * J * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->lamh, C * 4 * FSZ * b) && pl->alloc_adj(&pl->fwa, C * 14 * FSZ * b) &&
-         pl->alloc_adj(&pl->spart, C * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->ext, (size_t)4 * (p.Nx + 4) * p.N * p.N * b) &&
          pl->alloc_adj((void**)&pl->lflux, 2 * sizeof(double));
 }

@@ -18,7 +18,7 @@ bool collision_pipeline(qb_plan_s* pl, const T* w, T* c, int ncells, int cell0, 
     return pl->persistent ? std::min(ntask, persistent_grid(kern, NT)) : ntask;
   };
   id = pl->begin(QB_K_TERMS, s);
-  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(grid(ncells * 8, (const void*)qb::k_terms<T, P, E>)), dim3(NT),
+  hipLaunchKernelGGL((qb::k_terms<T, P, E>), dim3(grid(ncells * qb::kTermPlanes, (const void*)qb::k_terms<T, P, E>)), dim3(NT),
                      0, s, d, ncells);
   pl->end(id, s);
   id = pl->begin(QB_K_I3, s);

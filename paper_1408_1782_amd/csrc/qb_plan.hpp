@@ -68,7 +68,7 @@ struct qb_plan_s {
     int E = 0;
     bool built = false;
     void *tw = nullptr, *phip = nullptr, *Kt = nullptr, *psi = nullptr, *psip = nullptr, *psiw = nullptr,
-         *psips = nullptr;
+         *psips = nullptr, *negk = nullptr;
   };
   std::vector<TabSet> tabs;
   int cur_tab = 0;
@@ -80,7 +80,7 @@ struct qb_plan_s {
   bool adjoint = false;
   void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
        *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
-  void *fwa = nullptr, *spart = nullptr;
+  void *fwa = nullptr;
   void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
        *cg = nullptr, *g0 = nullptr, *ext = nullptr;
   double* lflux = nullptr;
@@ -159,6 +159,7 @@ inline DevPlan<T> devplan(qb_plan_s* pl, int tab) {
   d.psip = (const T*)ts.psip;
   d.psiw = (const T*)ts.psiw;
   d.psips = (const T*)ts.psips;
+  d.negk = (const unsigned*)ts.negk;
   d.phx = (const T*)pl->phx;
   d.phy = (const T*)pl->phy;
   d.wm = (const T*)pl->wm;
@@ -180,7 +181,6 @@ inline DevPlan<T> devplan(qb_plan_s* pl, int tab) {
   d.i3sb = (T*)pl->i3sb;
   d.gsum = (T*)pl->gsum;
   d.fwa = (T*)pl->fwa;
-  d.spart = (T*)pl->spart;
   d.i3t = (T*)pl->i3t;
   d.lamh = (T*)pl->lamh;
   return d;
