@@ -266,7 +266,7 @@ def run_adjoint(steps, every):
             "grad_norms": {"W0": float(gW.abs().max()), "B": float(gB.abs().max())}}
 
 
-def run_batch(steps, nprob, replays=1):
+def run_batch(steps, nprob, replays=1, sub_replays=None):
     """Batched throughput on the uneven-batch workload (64 periodic problems,
     Nx ~ U{32, 64, 128, 256, 512}, N ~ U{32, 64}, J = 32, M = N, B = 0,
     dt = 2.5e-4, float32 with float64 moments): tile and launch-shape
@@ -274,14 +274,15 @@ def run_batch(steps, nprob, replays=1):
     (capture, instantiation and its first launch, reported as capture_s),
     then that graph replayed `replays` times, each replay timed alone (the
     `value` is cells * steps * replays over the replay time).  The N = 64
-    problems alone are timed the same way as a second batch."""
+    problems alone are timed the same way as a second batch, with
+    `sub_replays` replays (default `replays`; 0 skips it)."""
     import torch
     import paper_1408_1782_amd as qb
     import workloads
 
     wls = workloads.batch_config(nprob, steps)
 
-    def one(sel, label):
+    def one(sel, label, replays):
         probs = [qb.Problem(w.Nx, w.N, w.J, w.M, w.L, w.R, "f32") for w in sel]
         batch = qb.Batch(probs)
         batch.tune()
@@ -306,8 +307,9 @@ def run_batch(steps, nprob, replays=1):
         return {"problems": len(sel), "cells": cells, "capture_s": capture, "replays": replays,
                 "replay_s": times, "value": cells * steps * replays / sum(times), "finite": finite}
 
-    full = one(wls, "all")
-    sub = one([w for w in wls if w.N == 64], "N=64")
+    full = one(wls, "all", replays)
+    sr = replays if sub_replays is None else sub_replays
+    sub = one([w for w in wls if w.N == 64], "N=64", sr) if sr > 0 else None
     return {"workload": "uneven_batch", "unit": "cells*steps/s", "dtype": "f32", "steps_per_graph": steps,
             "replayed_steps": steps * replays, "graph": "captured once, replayed", "all": full, "N64": sub,
             "N32_cells": sum(w.Nx for w in wls if w.N == 32)}
@@ -618,6 +620,8 @@ def main():
                     help="steps of the uneven-batch measurement (0 skips it)")
     ap.add_argument("--batch-problems", type=int, default=64, help="problems in the uneven batch")
     ap.add_argument("--batch-replays", type=int, default=1, help="timed replays of the recorded batch graph")
+    ap.add_argument("--batch-sub-replays", type=int, default=None,
+                    help="replays of the N = 64 sub-batch (default: --batch-replays; 0 skips it)")
     ap.add_argument("--batch-only", action="store_true", help="run only the uneven-batch measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 512 MiB device copy first (scale for HBM byte counters)")
@@ -644,7 +648,8 @@ def main():
         print(json.dumps(run_slab_record(args.slab_record)), flush=True)
         return
     if args.batch_only:
-        print(json.dumps(run_batch(args.batch_steps, args.batch_problems, args.batch_replays)), flush=True)
+        print(json.dumps(run_batch(args.batch_steps, args.batch_problems, args.batch_replays,
+                                   args.batch_sub_replays)), flush=True)
         return
 
     import workloads
@@ -738,7 +743,8 @@ def main():
         out["adjoint_forward_ratio"] = adj["ratio"]
         out["adjoint"] = adj
     if args.batch_steps > 0:
-        out["batched"] = run_batch(args.batch_steps, args.batch_problems, args.batch_replays)
+        out["batched"] = run_batch(args.batch_steps, args.batch_problems, args.batch_replays,
+                                   args.batch_sub_replays)
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -422,6 +422,15 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
   constexpr int F = I3Regs<T, P, E>::F;
   constexpr bool RREG = 2 * F + 2 * F + (WREG ? 2 * F : 0) + 4 * F + 48 <= I3Regs<T, P, E>::BUDGET;
   constexpr int RE = RREG ? E : 1;
+  // Two fields of LDS beside the transpose buffer, where they fit and the
+  // workgroup fills its compute unit anyway (512 threads or more): three
+  // private reads per nu (the old w_bar_nu
+  // before the q convolution, the old Y_nu and s_nu before the R
+  // convolution) are copied there by buffer-to-LDS loads issued before the
+  // convolution, so their latency hides behind its transforms.
+  constexpr bool STG = K::NT >= 512 && (K::LDS + 2 * K::FSZ) * (int)sizeof(T) <= 160 * 1024;
+  constexpr int PFD = STG ? K::FSZ * (int)sizeof(T) / 4 : 1;  // dwords of one staged field
+  __shared__ unsigned pfs[STG ? 2 * PFD : 1];
   __shared__ T smem[K::LDS];
   typename K::Eng eng;
   setup(eng, smem, d.tw);
@@ -558,7 +567,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
       for (int nu = 0; nu < 4; ++nu) {
         const T enu = nu == 0 ? (T)1 : (T)-1;  // eta_nu
         // q_a,nu = Psi(w_a s_nu); then R_a,nu = Psi(eta_a b_bar_nu s_a + eta_nu t_a w_nu)
+        if constexpr (STG) fetch_lds_dw<T, K::NT, E>(rg, pfs, vo, nu * K::FSZ * S);
         conv(zr, zi);
+        const unsigned pq = STG ? lds_fetch_wait() : 0u;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
@@ -566,19 +577,28 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
           const T ta0v = row(ta0, rt, a0, n), ta1v = row(ta1, rt, a1, n);
           ya0[n] += ea0 * bb * zr[n];
           ya1[n] -= bb * zi[n];
-          rmw(rg, nu, o, enu * c * (ta0v * zr[n] + ta1v * zi[n]));
+          const T gv = enu * c * (ta0v * zr[n] + ta1v * zi[n]);
+          if constexpr (STG)
+            bst<T>(rg, lds_elem<T, K::NT, E>(pfs, n, pq) + gv, vo, (nu * K::FSZ + o) * S);
+          else
+            rmw(rg, nu, o, gv);
           const T wv = enu * ld(rw, nu, o);
           zr[n] = ea0 * b * row(sa0, rb, a0, n) + wv * ta0v;
           zi[n] = wv * ta1v - b * row(sa1, rb, a1, n);
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (STG) {
+          fetch_lds_dw<T, K::NT, E>(rc, pfs, vo, nu * K::FSZ * S);
+          fetch_lds_dw<T, K::NT, E>(rb, pfs + PFD, vo, nu * K::FSZ * S);
+        }
         conv(zr, zi);
+        const unsigned pr2 = STG ? lds_fetch_wait() : 0u;
         // next q input: s of the next nu (re-read on the last pass, unused)
         const int nx = nu < 3 ? nu + 1 : 3;
 #pragma unroll
         for (int n = 0; n < E; ++n) {
           const unsigned o = n * K::NT;
-          const T sv = c * ld(rb, nu, o);
+          const T sv = c * (STG ? lds_elem<T, K::NT, E>(pfs + PFD, n, pr2) : ld(rb, nu, o));
           if constexpr (WREG) {
             wa0[WREG ? n : 0] += sv * zr[n];
             wa1[WREG ? n : 0] += sv * zi[n];
@@ -589,10 +609,8 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
           const T w0 = ld(rw, a0, o), w1 = ld(rw, a1, o);
           // first row pair: the old value is read (in bounds) but dropped by
           // a select, which keeps the loop free of branches
-          // first row pair: the old value is read (in bounds) but dropped by
-          // a select, which keeps the loop free of branches
           const unsigned yo = (nu * K::FSZ + o) * S;
-          const T yp = bld<T>(rc, vo, yo);
+          const T yp = STG ? lds_elem<T, K::NT, E>(pfs, n, pr2) : bld<T>(rc, vo, yo);
           bst<T>(rc, c * (w0 * zr[n] + w1 * zi[n]) + (mp != 0 ? yp : (T)0), vo, yo);
           const T sn = ld(rb, nx, o);
           zr[n] = w0 * sn;

@@ -132,6 +132,32 @@ __device__ __forceinline__ void fetch_lds(rsrc_t r, T* lds, unsigned voff, unsig
   for (int n = 0; n < E; ++n)
     __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(size_t)(lb + n * NT * 4), 4, voff, sb + n * NT * 4, 0, 0);
 }
+// The same for elements of any size: dword d of every element lands in LDS
+// plane d (NT E dwords each), read back with lds_elem.
+template <typename T, int NT, int E>
+__device__ __forceinline__ void fetch_lds_dw(rsrc_t r, unsigned* lds, unsigned voff, unsigned soff) {
+  typedef __attribute__((address_space(3))) void* lds_ptr;
+  constexpr int DW = (int)sizeof(T) / 4;
+  const unsigned wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  unsigned lb = (unsigned)(size_t)(__attribute__((address_space(3))) unsigned*)lds + 256u * wave;
+  unsigned sb = soff;
+  __asm__ volatile("" : "+s"(lb), "+s"(sb));
+#pragma unroll
+  for (int dw = 0; dw < DW; ++dw)
+#pragma unroll
+    for (int n = 0; n < E; ++n)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_ptr)(size_t)(lb + (dw * NT * E + n * NT) * 4), 4,
+                                               voff + 4 * dw, sb + n * NT * (int)sizeof(T), 0, 0);
+}
+template <typename T, int NT, int E>
+__device__ __forceinline__ T lds_elem(const unsigned* lds, int n, unsigned t) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, lds[n * NT + t]);
+  } else {
+    const unsigned long long lo = lds[n * NT + t], hi = lds[NT * E + n * NT + t];
+    return __builtin_bit_cast(T, lo | (hi << 32));
+  }
+}
 // Wait until every buffer load of this wavefront (the LDS copies included)
 // has completed; returns the thread index through the wait so that LDS
 // reads addressed with it cannot move above the wait.
