@@ -187,9 +187,14 @@ __global__ void k_assemble_vjp(DevPlan<T> d, int ncells, int fsz, int part) {
 // The field cotangents (acot[0..7]) depend only on lam and w, so they are
 // ready before this kernel; the dependence of the assembly on the fields
 // themselves (acot[12..15]) is formed after it.
+// Workgroups of 512 threads or more are held to 128 registers per lane,
+// so two of them share a compute unit: the kernel waits on its private
+// accumulators between transforms, and a second workgroup fills those
+// waits (measured at N = 32 in float64: -11 % with 15 registers spilled).
 constexpr int kTermsVjpTasks = kTermPlanes;
 template <typename T, int P, int E>
-__global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms_vjp(DevPlan<T> d) {
+__global__ __launch_bounds__((Fft2<T, P, E>::NT))
+__attribute__((amdgpu_waves_per_eu(Fft2<T, P, E>::NT >= 512 ? 4 : 1))) void k_terms_vjp(DevPlan<T> d) {
   using K = Kern<T, P, E>;
   constexpr unsigned S = sizeof(T);
   __shared__ T smem[K::LDS];
