@@ -454,10 +454,16 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
   const rsrc_t rc = mkbuf(d.i3sb + tb * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
+  // i3g planes 0..3 start at zero: with WREG their first touch is the q
+  // consumer of the first row pair (a select drops the old value); without
+  // it the R consumer touches a1 first, so they are cleared here.  Planes
+  // 4..7 take their first values at the first node pair (a select again).
+  if constexpr (!WREG) {
 #pragma unroll 1
-  for (int q = 0; q < 8; ++q)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int n = 0; n < E; ++n) bst<T>(rg, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+      for (int n = 0; n < E; ++n) bst<T>(rg, (T)0, vo, (q * K::FSZ + n * K::NT) * S);
+  }
   auto conv = [&](T (&zr)[E], T (&zi)[E]) {
     eng.fwd2(zr, zi);
 #pragma unroll
@@ -529,6 +535,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
 #pragma unroll 1
     for (int mp = 0; mp < 2; ++mp) {
       const int a0 = 2 * mp, a1 = 2 * mp + 1;
+      const bool first = m == 0 && mp == 0;
       const T ea0 = a0 == 0 ? (T)1 : (T)-1;  // eta_a0; eta_a1 = -1
       T ya0[E], ya1[E], wa0[WREG ? E : 1], wa1[WREG ? E : 1];
 #pragma unroll
@@ -583,10 +590,10 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
           ya0[n] += ea0 * bb * zr[n];
           ya1[n] -= bb * zi[n];
           const T gv = enu * c * (ta0v * zr[n] + ta1v * zi[n]);
-          if constexpr (STG)
-            bst<T>(rg, lds_elem<T, K::NT, E>(pfs, n, pq) + gv, vo, (nu * K::FSZ + o) * S);
-          else
-            rmw(rg, nu, o, gv);
+          {
+            const T gp = STG ? lds_elem<T, K::NT, E>(pfs, n, pq) : bld<T>(rg, vo, (nu * K::FSZ + o) * S);
+            bst<T>(rg, gv + (WREG && first ? (T)0 : gp), vo, (nu * K::FSZ + o) * S);
+          }
           const T wv = enu * ld(rw, nu, o);
           zr[n] = ea0 * b * row(sa0, rb, a0, n) + wv * ta0v;
           zi[n] = wv * ta1v - b * row(sa1, rb, a1, n);
@@ -635,9 +642,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
       }
     }
     // w_hat_bar += phase conj(F)(Y), packed pairs (0, 1), (2, 3).  Only its
-    // entries on Xi are read back (the input stage keeps Xi), so the other
-    // lanes' accesses get an offset past the buffer (loads 0, stores
-    // dropped; the planes were cleared in full at the start).
+    // entries on Xi are read back (k_grad_out keeps Xi and drops the rest
+    // with a select), so the other lanes' accesses get an offset past the
+    // buffer (loads 0, stores dropped) and those entries are never written.
     const int bx = centered<P>(kx);
     const bool kx_in = bx > -P / 4 && bx < P / 4;
 #pragma unroll 1
@@ -660,8 +667,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_i3_vjp_reg(DevPlan<T> d
         T xr, xi;
         cmul(zr[k], -zi[k], er, ei, xr, xi);
         const unsigned fr = ((4 + 2 * pr) * K::FSZ + o) * S, fi = ((5 + 2 * pr) * K::FSZ + o) * S;
-        bst<T>(rg, bld<T>(rg, vk, fr) + xr, vk, fr);
-        bst<T>(rg, bld<T>(rg, vk, fi) + xi, vk, fi);
+        const T g0 = bld<T>(rg, vk, fr), g1 = bld<T>(rg, vk, fi);
+        bst<T>(rg, xr + (m != 0 ? g0 : (T)0), vk, fr);
+        bst<T>(rg, xi + (m != 0 ? g1 : (T)0), vk, fi);
       }
     }
   }

@@ -54,7 +54,7 @@ struct DevPlan {
   T* wP;     // [cells][5][P*P]     w_mu and f0 = 2 w0 - 1 on the P grid, row real
   T* terms;  // [cells][11][P*P]    I_1 (3), I_4 (4), I_2 (one per Pauli component) real-space fields
   T* acc;    // [cells][7][2][P*P]  spectral accumulators of the I_1 / I_4 tasks
-  T* i3s;    // [cells][J][4][P*P]  shifted fields of the current (j, m)
+  T* i3s;    // [cells][J][4 or 6][P*P]  shifted fields of the current (j, m) (+ partner sums)
   T* i3o;    // [cells][J][4][P*P]  I_3 partial sums over m, per j
   T* i3sum;  // [cells][4][P*P]     assembled real-space fields of C
   T* i3p;    // [cells][J][4][P*P]  partner-node spectra of I_3 per j (2 packed pairs, re/im, col spec)
@@ -482,6 +482,12 @@ struct I3Regs {
   }
 };
 
+// Planes per (cell, j) of the shifted-field buffer i3s: the four shifted
+// fields, and in float64 two more for partner sums that do not fit in
+// registers.
+template <typename T>
+constexpr int kI3sPlanes = sizeof(T) == 8 ? 6 : 4;
+
 template <typename T>
 __device__ __forceinline__ T pick4(int i, T a, T b, T c, T d) {
   return i == 0 ? a : (i == 1 ? b : (i == 2 ? c : d));
@@ -492,6 +498,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   using K = Kern<T, P, E, true>;
   constexpr unsigned S = sizeof(T);
   constexpr bool SREG = I3Regs<T, P, E>::template sreg<PAIR>();
+  // Paired nodes keep the partner sums of a row pair in registers where the
+  // register plan allows (PREG); otherwise (float64 at P = 128, and the
+  // 32-element float64 tile at P = 64) they accumulate in two more planes
+  // of the shifted-field buffer (PMEM) instead of spilling.
+  constexpr bool PREG = PAIR && I3Regs<T, P, E>::PAIR;
+  constexpr bool PMEM = PAIR && !PREG;
+  static_assert(!(PMEM && SREG), "partner sums in memory need the shifted-field buffer");
   // the current row pair's two shifted fields in registers for the nu loop
   // (saves two field reads per convolution); fits the unpaired kernel with
   // at most 16 registers per field
@@ -527,7 +540,7 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
   const rsrc_t rw = mkbuf(d.wP + (size_t)cell * 5 * K::FSZ, 5 * K::FSZ);
   const rsrc_t ro = mkbuf(d.i3o + tb * 4 * K::FSZ, 4 * K::FSZ);
   const rsrc_t rp = mkbuf(d.i3p + tb * 4 * K::FSZ, 4 * K::FSZ);
-  const rsrc_t rb = mkbuf(SREG ? d.i3o : d.i3s + tb * 4 * K::FSZ, 4 * K::FSZ);
+  const rsrc_t rb = mkbuf(SREG ? d.i3o : d.i3s + tb * kI3sPlanes<T> * K::FSZ, kI3sPlanes<T> * K::FSZ);
   const rsrc_t rm = mkbuf(d.psips + (size_t)j * K::FSZ, K::FSZ);
   const int kx = eng.line;
   T s[SREG ? 4 : 1][SREG ? E : 1];
@@ -572,8 +585,9 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
     for (int mp = 0; mp < 2; ++mp) {
       const int m0 = 2 * mp, m1 = 2 * mp + 1;
       // partner sums of this pair of rows a = m0, m1 (sign of the B term folded in)
-      T pa[PAIR ? E : 1], pb[PAIR ? E : 1];
-      if constexpr (PAIR) {
+      // (in registers; with PMEM in planes 4, 5 of the shifted-field buffer)
+      T pa[PREG ? E : 1], pb[PREG ? E : 1];
+      if constexpr (PREG) {
 #pragma unroll
         for (int n = 0; n < E; ++n) pa[n] = pb[n] = 0;
       }
@@ -650,10 +664,17 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
             v += first ? (T)0 : prev;
             bst<T>(ro, v, vo, off);
           }
-          if constexpr (PAIR) {
+          if constexpr (PREG) {
             const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
-            pa[PAIR ? n : 0] += sa_sign * wv * zr[n];
-            pb[PAIR ? n : 0] += wv * zi[n];
+            pa[PREG ? n : 0] += sa_sign * wv * zr[n];
+            pb[PREG ? n : 0] += wv * zi[n];
+          } else if constexpr (PMEM) {
+            // first nu of the row pair: the old value is dropped by a select
+            const T wv = ew * bld<T>(rw, vo, (nu * K::FSZ + o) * S);
+            const unsigned qa = (4 * K::FSZ + o) * S, qb = (5 * K::FSZ + o) * S;
+            const T pva = bld<T>(rb, vo, qa), pvb = bld<T>(rb, vo, qb);
+            bst<T>(rb, sa_sign * wv * zr[n] + (nu != 0 ? pva : (T)0), vo, qa);
+            bst<T>(rb, wv * zi[n] + (nu != 0 ? pvb : (T)0), vo, qb);
           }
           if (n % SG == SG - 1) __builtin_amdgcn_sched_barrier(0);
         }
@@ -674,8 +695,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) __attribute__((amdgpu_waves_pe
         T zr[E], zi[E];
 #pragma unroll
         for (int n = 0; n < E; ++n) {
-          zr[n] = pa[PAIR ? n : 0];
-          zi[n] = pb[PAIR ? n : 0];
+          if constexpr (PMEM) {
+            zr[n] = bld<T>(rb, vo, (4 * K::FSZ + n * K::NT) * S);
+            zi[n] = bld<T>(rb, vo, (5 * K::FSZ + n * K::NT) * S);
+          } else {
+            zr[n] = pa[PREG ? n : 0];
+            zi[n] = pb[PREG ? n : 0];
+          }
         }
         eng.fwd2(zr, zi);
 #pragma unroll

@@ -98,12 +98,6 @@ void gauss_legendre(int M, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-// elements per thread of the FFT engine; must match qb::Cfg used by the kernels
-template <typename T, int P, int E>
-constexpr bool paired_t() {
-  return qb::I3Regs<T, P, E>::PAIR;
-}
-
 // Tile shapes (elements per thread E; lanes per line P / E) compiled for
 // each padded grid size; the first is the default, qb_plan_tune picks one.
 std::vector<int> tile_candidates(int P) {
@@ -111,20 +105,6 @@ std::vector<int> tile_candidates(int P) {
     case 32: return {16, 8};
     case 64: return {16, 32, 8};
     default: return {16, 32};
-  }
-}
-
-// default node pairing of the I_3 kernel of this tile (register plan)
-bool i3_paired(int precision, int P, int E) {
-  const bool d = precision == QB_F64;
-  switch (P) {
-    case 32: return E == 8 ? (d ? paired_t<double, 32, 8>() : paired_t<float, 32, 8>())
-                           : (d ? paired_t<double, 32, 16>() : paired_t<float, 32, 16>());
-    case 64: return E == 16 ? (d ? paired_t<double, 64, 16>() : paired_t<float, 64, 16>())
-                 : E == 8 ? (d ? paired_t<double, 64, 8>() : paired_t<float, 64, 8>())
-                          : (d ? paired_t<double, 64, 32>() : paired_t<float, 64, 32>());
-    default: return E == 16 ? (d ? paired_t<double, 128, 16>() : paired_t<float, 128, 16>())
-                            : (d ? paired_t<double, 128, 32>() : paired_t<float, 128, 32>());
   }
 }
 
@@ -265,7 +245,9 @@ bool select_tile(qb_plan_s* pl, int E) {
   pl->E = E;
   pl->TPR = pl->P / E;
   pl->NT = pl->P * pl->TPR;
-  pl->i3_pair = i3_paired(pl->prob.precision, pl->P, E);
+  // node pairing by default on every tile: its partner sums sit in registers,
+  // or in buffer planes where the register plan has no room for them
+  pl->i3_pair = true;
   return true;
 }
 
@@ -416,7 +398,7 @@ struct CollBufs {
 template <typename T>
 bool carve_collision(Arena& a, const qb_plan_s* pl, size_t C, CollBufs& b) {
   const size_t FSZ = (size_t)pl->P * pl->P, J = pl->prob.J, t = sizeof(T);
-  return a.take(&b.i3s, C * J * 4 * FSZ * t) && a.take(&b.spec, C * 8 * FSZ * t) &&
+  return a.take(&b.i3s, C * J * qb::kI3sPlanes<T> * FSZ * t) && a.take(&b.spec, C * 8 * FSZ * t) &&
          a.take(&b.wP, C * 5 * FSZ * t) && a.take(&b.terms, C * qb::kTermPlanes * FSZ * t) && a.take(&b.acc, C * 14 * FSZ * t) &&
          a.take(&b.i3o, C * J * 4 * FSZ * t) && a.take(&b.i3sum, C * 4 * FSZ * t) &&
          a.take(&b.i3p, C * J * 4 * FSZ * t) && a.take(&b.i3ps, C * 4 * FSZ * t);
@@ -894,7 +876,7 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
   const TuneKey key{p.precision, p.N, p.J, p.M, ncells};
   auto it = tune_cache().find(key);
   int best = cands[0];
-  bool best_pair = i3_paired(p.precision, pl->P, best);
+  bool best_pair = true;
   if (it != tune_cache().end()) {
     best = it->second / 2;
     best_pair = it->second % 2 == 1;
