@@ -314,6 +314,42 @@ def run_batch(steps, nprob, replays=1, sub_replays=None):
             "N32_cells": sum(w.Nx for w in wls if w.N == 32)}
 
 
+BATCH_RECORD = os.path.join(HERE, "profiles", "batch_uneven_64problems_50steps.json")
+
+
+def batch_record():
+    """The committed 50-step run of the uneven batch (a 5-step graph
+    captured once and replayed 10 times, about 14 minutes, too long for the
+    default line): its command, replayed steps and cells*steps/s, or None."""
+    try:
+        with open(BATCH_RECORD) as f:
+            r = json.load(f)
+        a = r["result"]["all"]
+        return {"file": os.path.relpath(BATCH_RECORD, HERE), "command": r["command"],
+                "replayed_steps": r["result"]["replayed_steps"], "capture_s": a["capture_s"],
+                "value": a["value"], "unit": r["result"]["unit"]}
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+SLAB_RECORD = os.path.join(HERE, "profiles", "slab_dirichlet_maxwell_500steps_f32.json")
+
+
+def slab_record():
+    """The committed 500-step float32 run of the slab (about 5 minutes):
+    its command and the final drift and budget residuals, or None."""
+    try:
+        with open(SLAB_RECORD) as f:
+            r = json.load(f)
+        last = r["result"]["record"][-1]
+        return {"file": os.path.relpath(SLAB_RECORD, HERE), "command": r["command"], "steps": last["step"],
+                "cells*steps/s": r["result"]["cells*steps/s"],
+                **{k: last[k] for k in ("density_drift", "energy_drift", "density_budget_residual",
+                                        "energy_budget_residual")}}
+    except (OSError, ValueError, KeyError, IndexError):
+        return None
+
+
 def run_slab_record(steps, chunk=25):
     """The wall-bounded slab in float32 (float64 moments) for `steps` steps
     from its initial state, in calls of `chunk` steps: the total moments
@@ -744,6 +780,12 @@ def main():
     if args.batch_steps > 0:
         out["batched"] = run_batch(args.batch_steps, args.batch_problems, args.batch_replays,
                                    args.batch_sub_replays)
+        rec = batch_record()
+        if rec is not None:
+            out["batched_record"] = rec
+    rec = slab_record()
+    if rec is not None:
+        out["slab_record"] = rec
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(wl)

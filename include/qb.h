@@ -294,8 +294,9 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
  * ncells) for the life of the process.  *tile (may be NULL) receives E. */
 qb_status qb_plan_tune(qb_plan plan, int32_t ncells, int32_t* tile, void* stream);
 
-/* I_3 kernel with (1) or without (0) Gauss-Legendre node pairing; both
- * compute the same operator (the pairing uses rho_{M-1-m} = -rho_m). */
+/* I_3 kernel with (1, the default on every tile) or without (0)
+ * Gauss-Legendre node pairing; both compute the same operator (the pairing
+ * uses rho_{M-1-m} = -rho_m). */
 qb_status qb_plan_set_pairing(qb_plan plan, int32_t paired);
 
 /* Tile shape E of the reverse-mode pipeline (qb_collision_vjp and the
