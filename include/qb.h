@@ -286,7 +286,8 @@ qb_status qb_plan_set_tile(qb_plan plan, int32_t E);
 /* Autotuner: time the collision pipeline on the plan's first `ncells` cells
  * for every compiled tile shape, with and without Gauss-Legendre node
  * pairing in the I_3 kernel, and keep the fastest; then the two launch
- * shapes (qb_plan_set_persistent) on that tile; when the plan's
+ * shapes (qb_plan_set_persistent) on that tile, the persistent one kept
+ * only when it is more than 1 % faster; when the plan's
  * adjoint is enabled, also time the reverse-mode pipeline for every tile
  * shape and both I_3 adjoint kernels (row w cotangents in memory or in
  * registers, see qb_plan_config) and keep the fastest.  Synchronous; overwrites the

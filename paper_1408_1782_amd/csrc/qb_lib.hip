@@ -944,7 +944,9 @@ qb_status do_tune(qb_plan_s* pl, int ncells, int* chosen, hipStream_t s) {
       pl->pool.push_back(a);
       pl->pool.push_back(b);
       pl->profiling = prof;
-      pl->persistent = t[1] < t[0];
+      // the two shapes tie within the timing noise on launches that fill the
+      // machine; the persistent grid has to win by more than 1 %
+      pl->persistent = t[1] < 0.99f * t[0];
       tune_cache()[pkey] = pl->persistent ? 1 : 0;
     }
   }
