@@ -64,7 +64,6 @@ struct DevPlan {
   T* acot;   // [cells][16][P*P]    assembly cotangents: g (3), y (4), S (1), b (4), w direct (4)
   T* gspec;  // [cells][11][2][P*P] cotangents of w_hat from I_1 (3), I_4 (4), I_2 (4), col spec
   T* gf0;    // [cells][7][P*P]     f0 cotangents of the I_1 / I_4 tasks, row real
-  T* tsb;    // [cells][11][2][P*P] scratch of the I_1 / I_4 / I_2 adjoint tasks
   T* i3g;    // [cells][J][8][P*P]  I_3 adjoint per (cell, j): w cotangent (4, row real),
              //                     packed w_hat cotangents (2 pairs x re/im, col spec)
   T* i3sb;   // [cells][J][4][P*P]  cotangent of the shifted fields of the current (j, m)

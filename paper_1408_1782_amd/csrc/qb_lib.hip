@@ -439,7 +439,6 @@ bool build_adjoint(qb_plan_s* pl) {
     if (!pl->alloc_adj(q, st)) return false;
   return pl->alloc_adj(&pl->lamP, C * 4 * FSZ * b) && pl->alloc_adj(&pl->acot, C * 16 * FSZ * b) &&
          pl->alloc_adj(&pl->gspec, C * 22 * FSZ * b) && pl->alloc_adj(&pl->gf0, C * 7 * FSZ * b) &&
-         pl->alloc_adj(&pl->tsb, C * 2 * qb::kTermsVjpTasks * FSZ * b) &&
          pl->alloc_adj(&pl->i3g, C * J * 8 * FSZ * b) && pl->alloc_adj(&pl->i3sb, C * J * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->gsum, C * 8 * FSZ * b) && pl->alloc_adj(&pl->i3t, C * J * 4 * FSZ * b) &&
          pl->alloc_adj(&pl->lamh, C * 4 * FSZ * b) && pl->alloc_adj(&pl->fwa, C * 14 * FSZ * b) &&

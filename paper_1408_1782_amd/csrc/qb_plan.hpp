@@ -78,7 +78,7 @@ struct qb_plan_s {
   double* flux;
   // adjoint workspace (qb_plan_enable_adjoint)
   bool adjoint = false;
-  void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *tsb = nullptr, *i3g = nullptr,
+  void *lamP = nullptr, *acot = nullptr, *gspec = nullptr, *gf0 = nullptr, *i3g = nullptr,
        *i3sb = nullptr, *gsum = nullptr, *i3t = nullptr, *lamh = nullptr;
   void *fwa = nullptr;
   void *wn = nullptr, *wa = nullptr, *w1 = nullptr, *wb = nullptr, *lb = nullptr, *ls = nullptr, *la = nullptr,
@@ -176,7 +176,6 @@ inline DevPlan<T> devplan(qb_plan_s* pl, int tab) {
   d.acot = (T*)pl->acot;
   d.gspec = (T*)pl->gspec;
   d.gf0 = (T*)pl->gf0;
-  d.tsb = (T*)pl->tsb;
   d.i3g = (T*)pl->i3g;
   d.i3sb = (T*)pl->i3sb;
   d.gsum = (T*)pl->gsum;
