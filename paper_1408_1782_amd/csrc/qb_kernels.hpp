@@ -440,13 +440,13 @@ __global__ __launch_bounds__((Fft2<T, P, E>::NT)) void k_terms(DevPlan<T> d, int
 // Register plan.  One workgroup of NT threads puts NT / 256 waves on each
 // SIMD (at least one), so a thread may hold 512 / that many VGPRs (at most
 // 256).  The working field takes 2 E values; the partner sums of a row pair
-// 2 E more (PAIR: node pairing pays only while they stay in registers); the
-// four shifted fields 4 E more (SREG: otherwise they go through a
-// per-workgroup buffer).  About 48 VGPRs go to addresses and temporaries.
-// (The thresholds were checked against the compiler's register reports for
-// every compiled tile: no scratch spills except where noted.)
-// PAIR is the default; the kernel is compiled both ways and the tuner may
-// pick pairing where its partner sums spill (it can still win).
+// 2 E more (PAIR: in registers where they fit, otherwise in two planes of
+// the shifted-field buffer); the four shifted fields 4 E more (SREG:
+// otherwise they go through a per-workgroup buffer).  About 48 VGPRs go to
+// addresses and temporaries.  (The thresholds were checked against the
+// compiler's register reports for every compiled tile.)  The kernel is
+// compiled with and without node pairing; pairing is the default on every
+// tile and wins on each.
 template <typename T, int P, int E>
 struct I3Regs {
   static constexpr int NT = P * (P / E);
